@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Throughput of the ADER-WENO Euler zone update on one MI355X.
+
+Workload: 3D Euler, ideal gas gamma = 1.4, the isentropic vortex extruded
+along z with a seeded smooth density perturbation (amplitude 1e-2, 4 Fourier
+modes per axis), 128^3 zones on the periodic box [0,10]^3, fourth-order
+WENO + ADER, HLLC, CFL 0.4, FP64, steps with the CFL time step computed on the
+device.  Prints one JSON line (the metric is zone updates per second).
+
+The timed region holds K full steps (ghost fill, reconstruction, predictor,
+Riemann solver, update and CFL reduction) with the state resident in HBM,
+bracketed by device synchronisation.  Per-stage times come from HIP events
+recorded by the library on the stream its kernels run on.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "zone-updates/sec, 3D Euler WENO+ADER, FP64 vs FP32+learned gate at stated L1"
+UNIT = "zone-updates/s"
+PEAK_FP64_VALU_TFLOPS = 78.6          # MI355X published FP64 vector peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_predictor_vortex3d_128.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2211_13295_amd", "csrc", f)
+                  for f in ("hog_kernels.h", "hog_physics.h", "hog_tables.h")]
+
+
+def _binom(n, k):
+    return math.comb(n, k)
+
+
+def spatial_eval_fma(D, L, N1):
+    """FMAs to evaluate (or, transposed, to project onto) the total-degree-L
+    spatial modes at the N1^D tensor Gauss nodes by sum factorisation."""
+    if D == 3:
+        return N1 * _binom(L + 3, 3) + N1 ** 2 * _binom(L + 2, 2) + N1 ** 3 * (L + 1)
+    return N1 * _binom(L + 2, 2) + N1 ** 2 * (L + 1)
+
+
+def predictor_flops(D, P):
+    """Algorithmic FP64 flops of the ADER predictor for one zone (FMA = 2).
+
+    Formulation: P Picard iterations; the first on the spatial nodes only
+    (the initial iterate does not depend on time), the others on the
+    (P+1)^(D+1) space-time Gauss nodes: evaluate the space-time modes by sum
+    factorisation (spatial transform of each time mode, Horner in time),
+    physical fluxes of all D axes, contraction against the P time modes that
+    feed a derivative, sum-factorised spatial L2 projection of each
+    (axis, time mode, variable), derivative / time-integral assembly; then the
+    face-point states (normal-axis contraction, tangential x time transform
+    at 2^D points) for the Riemann solver.  Division counted as one flop.
+    """
+    N1, NV = P + 1, D + 2
+    ns, nst = _binom(P + D, D), _binom(P + D + 1, D + 1)
+    flux_node = D * D + 5 * D + 5                 # 1/rho, velocities, pressure, D flux vectors
+    total = 0
+    for it in range(P):
+        if it == 0:
+            ev = spatial_eval_fma(D, P, N1) * NV
+            nodes = N1 ** D
+            ne = 1
+            tcon = 0
+        else:
+            ev = (sum(spatial_eval_fma(D, P - e, N1) for e in range(P + 1)) + N1 ** (D + 1) * P) * NV
+            nodes = N1 ** (D + 1)
+            ne = P
+            tcon = nodes * D * ne * NV                # FMAs
+        proj = D * NV * sum(spatial_eval_fma(D, P - e, N1) for e in range(ne))
+        # derivative / time-integral assembly: one FMA per (axis, source, target) term
+        asm = D * (nst - ns) * NV * P
+        total += 2 * (ev + tcon + proj + asm) + nodes * flux_node
+    # face-point states: per face side contract the normal axis, then the
+    # (D-1 spatial + time) polynomial of degree P at 2^D points
+    face_side = nst + sum(2 ** (k + 1) * _binom(P + D - k, D - k) for k in range(D))
+    total += 2 * D * 2 * face_side * NV
+    return total
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record():
+    """HBM bytes per predictor launch measured with rocprofv3 counters, if the
+    kernel sources have not changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(order, seconds):
+    """The CPU oracle (plain FP64 C, OpenMP over zones) timed on this host on a
+    bounded sample: whole steps of the same 3D workload at 32^3 (per-zone work
+    of the scheme does not depend on the grid size)."""
+    import icgen
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    n = 32
+    pb = icgen.vortex3d_perturbed(n=n, seed=2)
+    c = oracle.cfg_from_problem(pb, order)
+    U = pb.U
+    dt, _ = oracle.cfl_dt(c, U)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        U = oracle.step(c, U, dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 50:
+            break
+    return {"value": n ** 3 * steps / el, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full fourth-order steps of the same 3D workload at {n}^3 "
+                      f"({el:.1f} s, OpenMP threads={threads})"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the multi-GPU path (halo exchange and a min "
+              "all-reduce of dt) is a design note, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import icgen
+    from paper_2211_13295_amd import hog
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    hog.load()
+    n, order = args.n, args.order
+    pb = icgen.vortex3d_perturbed(n=n, seed=2)
+    g = hog.Grid.from_problem(pb, order)
+    if args.warmup > 0:
+        g.advance(args.warmup)
+    g.set_state(pb.U)
+    torch.cuda.synchronize()
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.advance(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile_read()
+    g.profile(False)
+    elapsed = t1 - t0
+    zones = n ** 3
+    value = zones * args.steps / elapsed
+    ms_step = elapsed * 1e3 / args.steps
+
+    D, P = 3, order - 1
+    zones_per_launch = (n + 2) ** 3                       # predictor runs on the interior grown by one zone
+    pflops = predictor_flops(D, P) * zones_per_launch
+    pred_ms, pred_calls = prof["predictor"]
+    avg_s = pred_ms / 1e3 / max(pred_calls, 1)
+    achieved = pflops / avg_s / 1e12
+    traffic = traffic_record()
+    stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()}
+    step_sum = sum(v[0] for v in prof.values()) / args.steps
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"3D Euler isentropic vortex extruded along z + seeded density modes "
+                               f"(amp 1e-2, 4 per axis), {n}^3 periodic [0,10]^3, order {order} "
+                               f"WENO+ADER, HLLC, CFL 0.4, FP64",
+                   "zones": zones, "order": order, "riemann": "hllc", "precision": "fp64"},
+        "roofline": {"bound": "alu", "kernel": "k_predict (ADER predictor)", "achieved": achieved,
+                     "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": traffic,
+                     "alg_flops_per_zone": predictor_flops(D, P), "zones_per_launch": zones_per_launch,
+                     "avg_launch_ms": avg_s * 1e3},
+        "stages_ms_per_launch": stage_ms,
+        "predictor_fraction_of_step": prof["predictor"][0] / args.steps / step_sum if step_sum > 0 else None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(order, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

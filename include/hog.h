@@ -1,0 +1,180 @@
+/*
+ * hog.h -- C ABI of the MI355X (gfx950) ADER-WENO zone update for the 2D/3D
+ * compressible Euler equations of an ideal gas.
+ *
+ * One call of hog_step() performs the three-stage update the paper builds its
+ * GPU codes on (arXiv 2211.13295, Sec. I.1 and Sec. II.1, Figs. 1-7):
+ *   WENO reconstruction of the conserved variables in every zone,
+ *   an ADER predictor that extends each zone polynomial in time,
+ *   a Riemann-solver (HLLC/HLL/Rusanov) corrector with a conservative
+ *   flux-difference update, and the CFL time step of the new state.
+ * The state lives in device memory between calls: the paper's per-step host
+ * round trip of the zone means (its "U_skinny" transfer, Sec. II.1, Fig. 1)
+ * only happens when the caller asks for it with hog_get_state().
+ *
+ * Conventions
+ *  - Every call returns an int status: HOG_OK (0) or a negative HOG_E* code;
+ *    hog_last_error() gives a message (thread-local, static storage).
+ *    Nothing is printed and nothing aborts.
+ *  - State layout HOG_SOA: double U[nv][nz][ny][nx] (x fastest), nv = ndim+2,
+ *    variables rho, rho*u, rho*v, [rho*w], E; in 2D nz = 1.  HOG_AOS:
+ *    double U[nz][ny][nx][nv] (the paper's zone-mean array order).
+ *  - Device memory: the caller allocates one workspace of
+ *    hog_workspace_size() bytes (e.g. a torch uint8 tensor) and keeps it alive
+ *    as long as the handle; the library allocates no device memory itself.
+ *  - Stream: all work is enqueued on the hipStream_t given at hog_create();
+ *    calls return without synchronising unless stated.  One handle must not
+ *    be used from two threads at once.
+ */
+#ifndef HOG_H
+#define HOG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HOG_ABI_VERSION 1
+
+enum {
+    HOG_OK = 0,
+    HOG_EINVAL = -1,     /* bad argument or configuration */
+    HOG_ENOMEM = -2,     /* workspace too small */
+    HOG_EDEVICE = -3,    /* HIP runtime error or unsupported device */
+    HOG_ENONPHYS = -4,   /* rho <= 0, p <= 0 or non-finite value in a zone */
+    HOG_ESTATE = -5      /* call out of order (e.g. step before set_state) */
+};
+
+enum { HOG_PERIODIC = 0, HOG_OUTFLOW = 1 };            /* per-axis boundary */
+enum { HOG_HLLC = 0, HOG_HLL = 1, HOG_RUSANOV = 2 };   /* Riemann solver */
+enum { HOG_FP64 = 0 };                                 /* arithmetic of the path */
+enum { HOG_SOA = 0, HOG_AOS = 1 };                     /* state layouts */
+enum { HOG_HOST = 0, HOG_DEVICE = 1 };                 /* where a user buffer lives */
+
+/* Debug taps (hog_debug_tap): intermediates of the last hog_step(). */
+enum {
+    HOG_TAP_MODES = 1,   /* spatial modes after reconstruction: double [N][ns][nv] */
+    HOG_TAP_STMODES = 2, /* space-time modes after the predictor: double [N][nst][nv]
+                            (needs debug = 1 in the config) */
+    HOG_TAP_FLUX_X = 3,  /* face fluxes: double [nv][nz][ny][nx+1] (x faces)      */
+    HOG_TAP_FLUX_Y = 4,  /*              double [nv][nz][ny+1][nx]                */
+    HOG_TAP_FLUX_Z = 5   /*              double [nv][nz+1][ny][nx]                */
+};
+/* N = nx*ny*nz interior zones in x-fastest order; modes are listed in the
+ * canonical order: space-time modes (a,b,c,e) with a+b+c+e <= p, e outermost,
+ * then c, then b, then a innermost (c = 0 in 2D); the spatial modes are the
+ * e = 0 block.  Mode (a,b,c,e) multiplies P_a(xi) P_b(eta) P_c(zeta) tau^e,
+ * P_k the monic Legendre polynomials on the zone [-1/2,1/2] and tau in [0,1]
+ * the fraction of the time step. */
+
+typedef struct hog_config {
+    int ndim;            /* 2 or 3 */
+    int nx, ny, nz;      /* interior zones per axis (nz = 1 in 2D), each >= 1 */
+    int order;           /* 3 or 4 (polynomial degree p = order - 1) */
+    int riemann;         /* HOG_HLLC | HOG_HLL | HOG_RUSANOV */
+    int bc[3];           /* per axis HOG_PERIODIC | HOG_OUTFLOW */
+    int precision;       /* HOG_FP64 */
+    int linear_weno;     /* 1: WENO nonlinear weights replaced by the linear ones */
+    int debug;           /* 1: keep the space-time modes for HOG_TAP_STMODES */
+    int positivity;      /* 1: a zone whose predictor meets rho <= 0, p <= 0 or a
+                            non-finite state at any quadrature node or face point
+                            falls back to its zone mean (first order) for that step */
+    int reserved[3];     /* must be 0 */
+    double gamma;        /* ratio of specific heats, > 1 */
+    double dx, dy, dz;   /* zone widths (dz ignored in 2D), > 0 */
+    double cfl;          /* CFL number of hog_compute_dt / dt_next, in (0, 1] */
+    double weno_eps;     /* epsilon of the nonlinear weights; <= 0 selects 1e-12 */
+    double g3[3];        /* O3 linear weights L, C, R; all 0 selects (0.075, 0.85, 0.075) */
+    double g4[4];        /* O4 linear weights H, L, C, R; all 0 selects
+                            (0.85, 0.01125, 0.1275, 0.01125) */
+} hog_config;
+
+typedef struct hog_grid hog_grid;
+
+/* ABI version of the loaded library (HOG_ABI_VERSION). */
+int hog_abi_version(void);
+
+/* Device bytes the caller must provide to hog_create() for this config.
+ * Errors: HOG_EINVAL for an invalid config or NULL pointer. */
+int hog_workspace_size(const hog_config* cfg, size_t* bytes);
+
+/* Bind a config, a device workspace (>= hog_workspace_size bytes, 256-byte
+ * aligned) and a HIP stream (NULL = default stream) to a new handle.  The
+ * handle borrows the workspace and the stream; both must outlive it.  The
+ * current HIP device must be a gfx950 GPU.
+ * Errors: HOG_EINVAL, HOG_ENOMEM (workspace too small), HOG_EDEVICE. */
+int hog_create(const hog_config* cfg, void* workspace, size_t bytes, void* hip_stream,
+               hog_grid** out);
+
+/* Release the handle (not the workspace or stream).  NULL is allowed. */
+int hog_destroy(hog_grid* g);
+
+/* Copy the interior state in (layout HOG_SOA | HOG_AOS, buffer on HOG_HOST |
+ * HOG_DEVICE, nv*nx*ny*nz doubles).  Stream-ordered; host buffers are copied
+ * before return.  Also evaluates the CFL reduction of the new state.
+ * Errors: HOG_EINVAL, HOG_EDEVICE. */
+int hog_set_state(hog_grid* g, const double* U, int layout, int where);
+
+/* Copy the current interior state out (same layouts).  For a host buffer the
+ * call synchronises the stream.  Errors: HOG_EINVAL, HOG_ESTATE, HOG_EDEVICE. */
+int hog_get_state(hog_grid* g, double* U, int layout, int where);
+
+/* CFL time step of the current state, dt = cfl / max_zones sum_d
+ * (|u_d| + c) / dx_d (paper Fig. 7, Eval_Tstep_Ptwise with a min reduction).
+ * Synchronises.  Errors: HOG_ENONPHYS (see hog_last_bad_zone), HOG_ESTATE. */
+int hog_compute_dt(hog_grid* g, double* dt);
+
+/* One ADER-WENO step with time step dt > 0.  If dt_next is not NULL the call
+ * synchronises, checks the new state and returns its CFL time step; on a
+ * non-physical new state it returns HOG_ENONPHYS and keeps the pre-step
+ * state as the current one.  If dt_next is NULL nothing is checked and the
+ * call does not synchronise.
+ * Errors: HOG_EINVAL (dt <= 0 or not finite), HOG_ESTATE, HOG_ENONPHYS. */
+int hog_step(hog_grid* g, double dt, double* dt_next);
+
+/* Advance with the CFL time step computed on the device from each state (no
+ * host round trip per step).  t_end <= 0: exactly nsteps steps.  t_end > 0:
+ * steps until the accumulated time reaches t_end, clipping the last step
+ * (this mode synchronises once per step); nsteps is then an upper bound.
+ * *t_out (may be NULL) receives the time advanced.  Synchronises at the end
+ * and checks the final state.  Errors: HOG_EINVAL, HOG_ESTATE, HOG_ENONPHYS. */
+int hog_advance(hog_grid* g, int nsteps, double t_end, double* t_out);
+
+/* Copy an intermediate of the last step to host memory dst (HOG_TAP_*).
+ * Synchronises.  Errors: HOG_EINVAL (unknown tap, bytes too small, tap not
+ * kept), HOG_ESTATE (no step yet). */
+int hog_debug_tap(hog_grid* g, int tap, void* dst, size_t bytes);
+
+/* Stage timing with HIP events recorded on the handle's stream around every
+ * stage of every subsequent step: 0 ghost fill, 1 reconstruction sweeps,
+ * 2 ADER predictor, 3 Riemann solver, 4 update + CFL (HOG_NSTAGES).  Used to
+ * split step time the way the paper splits out the predictor (Sec. III.1,
+ * Table III).  enable = 0 stops recording.  Errors: HOG_EINVAL, HOG_EDEVICE. */
+#define HOG_NSTAGES 5
+int hog_profile_enable(hog_grid* g, int enable);
+
+/* Total milliseconds and launch count per stage since the last enable/read
+ * (arrays of nstages >= HOG_NSTAGES entries); synchronises and resets the
+ * counters.  Errors: HOG_EINVAL, HOG_EDEVICE. */
+int hog_profile_read(hog_grid* g, double* ms, int* launches, int nstages);
+
+/* Device-side counters of the last step (synchronises): *t time advanced
+ * since the last hog_advance/hog_set_state, *dt the last time step,
+ * *fallback_zones the predictor zones (interior grown by one zone per axis)
+ * that used the positivity fallback in the last step.  Pointers may be NULL.
+ * Errors: HOG_EINVAL, HOG_EDEVICE. */
+int hog_stats(hog_grid* g, double* t, double* dt, long long* fallback_zones);
+
+/* Zone index (x fastest) of the first non-physical zone found by the last
+ * check, or -1. */
+long long hog_last_bad_zone(hog_grid* g);
+
+/* Message of the last error on this thread ("" if none). */
+const char* hog_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOG_H */

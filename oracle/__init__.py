@@ -38,7 +38,7 @@ class OCfg(C.Structure):
     _fields_ = [
         ("ndim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
         ("order", C.c_int), ("riemann", C.c_int), ("bc", C.c_int * 3),
-        ("linear_weno", C.c_int),
+        ("linear_weno", C.c_int), ("positivity", C.c_int),
         ("gamma", C.c_double), ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
         ("cfl", C.c_double), ("weno_eps", C.c_double),
         ("g3", C.c_double * 3), ("g4", C.c_double * 4),
@@ -64,6 +64,8 @@ def lib():
         cp = C.POINTER(OCfg)
         L.oracle_step.argtypes = [cp, dp, C.c_double, dp]
         L.oracle_step.restype = C.c_int
+        L.oracle_step_count.argtypes = [cp, dp, C.c_double, dp, C.POINTER(C.c_longlong)]
+        L.oracle_step_count.restype = C.c_int
         L.oracle_step_zones.argtypes = [cp, dp, C.c_double, C.c_int, ip, dp]
         L.oracle_step_zones.restype = C.c_int
         L.oracle_cfl_dt.argtypes = [cp, dp, C.POINTER(C.c_longlong)]
@@ -75,6 +77,7 @@ def lib():
         L.oracle_weno1d.argtypes = [cp, C.c_int, dp, dp]
         L.oracle_recon_block.argtypes = [cp, dp, dp]
         L.oracle_predict.argtypes = [cp, dp, dp, dp]
+        L.oracle_predict.restype = C.c_int
         L.oracle_eval_q.argtypes = [cp, dp, C.c_double, C.c_double, C.c_double, C.c_double, dp]
         L.oracle_riemann.argtypes = [cp, C.c_int, dp, dp, dp]
         L.oracle_phys_flux.argtypes = [cp, C.c_int, dp, dp]
@@ -92,7 +95,7 @@ def lib():
 
 
 def make_cfg(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("periodic",) * 3,
-             linear_weno=False, eps=DEFAULT_EPS, g3=DEFAULT_G3, g4=DEFAULT_G4):
+             linear_weno=False, eps=DEFAULT_EPS, g3=DEFAULT_G3, g4=DEFAULT_G4, positivity=True):
     c = OCfg()
     c.ndim = ndim
     c.nx, c.ny, c.nz = int(n[0]), int(n[1]), int(n[2]) if ndim == 3 else 1
@@ -102,6 +105,7 @@ def make_cfg(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("periodi
         b = bc[d]
         c.bc[d] = BC[b] if isinstance(b, str) else int(b)
     c.linear_weno = int(bool(linear_weno))
+    c.positivity = int(bool(positivity))
     c.gamma = gamma
     c.dx, c.dy, c.dz = h
     c.cfl = cfl
@@ -146,6 +150,17 @@ def step(cfg, U, dt):
     if rc != 0:
         raise MemoryError("oracle_step failed")
     return out
+
+
+def step_count(cfg, U, dt):
+    """One step; returns (U_new, number of predictor zones that used the fallback)."""
+    U = _state(U)
+    out = np.empty_like(U)
+    n = C.c_longlong(0)
+    rc = lib().oracle_step_count(C.byref(cfg), U, float(dt), out, C.byref(n))
+    if rc != 0:
+        raise MemoryError("oracle_step failed")
+    return out, n.value
 
 
 def step_zones(cfg, U, dt, ijk):

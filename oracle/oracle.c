@@ -51,6 +51,7 @@ typedef struct {
     int riemann;       /* 0 HLLC, 1 HLL, 2 Rusanov */
     int bc[3];         /* per axis: 0 periodic, 1 outflow (zero gradient) */
     int linear_weno;   /* 1: nonlinear weights replaced by the linear ones */
+    int positivity;    /* 1: first-order fallback in zones with an inadmissible predicted state */
     double gamma;
     double dx, dy, dz;
     double cfl;
@@ -174,6 +175,13 @@ static double pressure(const ocfg *c, const double *U)
     for (int d = 0; d < c->ndim; ++d) ke += U[1 + d] * U[1 + d];
     ke = 0.5 * ke / rho;
     return (c->gamma - 1.0) * (U[nv - 1] - ke);
+}
+
+/* A state the Euler fluxes are defined for: rho > 0, p > 0, both finite. */
+static int admissible(const ocfg *c, const double *U)
+{
+    double p = pressure(c, U);
+    return U[0] > 0.0 && p > 0.0 && isfinite(U[0]) && isfinite(p);
 }
 
 /* Physical flux of the Euler equations along axis dir. */
@@ -407,8 +415,9 @@ void oracle_eval_q(const ocfg *cf, const double *q, double xi, double eta, doubl
  * with Proj the L2 projection onto the space-time total-degree-p span of
  * leg x leg x leg x sleg computed with the tensor Gauss rule of p+1 points per
  * axis on [-1/2,1/2]^d x [0,1]. */
-void oracle_predict(const ocfg *cf, const double *lam, const double *W, double *q)
+int oracle_predict(const ocfg *cf, const double *lam, const double *W, double *q)
 {
+    int troubled = 0;
     int nd = cf->ndim, nv = nd + 2, p = cf->order - 1, n1 = p + 1;
     mode4 m[MAXST];
     int nst = st_modes(nd, p, m);
@@ -432,6 +441,7 @@ void oracle_predict(const ocfg *cf, const double *lam, const double *W, double *
                         double wt = gw[ix] * gw[jy] * gw[lt] * ((nd == 3) ? gw[kz] : 1.0);
                         double U[MAXV], F[3][MAXV];
                         eval_modes(nv, nst, m, q, xi, eta, zeta, tau, U);
+                        if (!admissible(cf, U)) troubled = 1;
                         for (int d = 0; d < nd; ++d) phys_flux(cf, d, U, F[d]);
                         for (int i = 0; i < nst; ++i) {
                             double phi = leg(m[i].a, xi) * leg(m[i].b, eta) * leg(m[i].c, zeta)
@@ -467,6 +477,7 @@ void oracle_predict(const ocfg *cf, const double *lam, const double *W, double *
             }
         memcpy(q, qn, sizeof(double) * nst * nv);
     }
+    return troubled;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -531,13 +542,55 @@ static void gather_block(const grid_t *g, const double *P, int i, int j, int k, 
 }
 
 /* Reconstruction + predictor of one zone from the padded array. */
-static void zone_q(const ocfg *c, const grid_t *g, const double *P, const double *lam,
-                   int i, int j, int k, double *q)
+/* Coordinates of face point (dir, side, pt) of a zone: side 0 is the face at
+ * xi_dir = -1/2, side 1 the face at +1/2; pt enumerates the 2-point Gauss
+ * rule in time (slowest), the first and the second tangential axis. */
+static void face_point(int nd, int dir, int side, int pt, double *x, double *tau)
+{
+    double g = 0.5 / sqrt(3.0);
+    int t1 = (dir == 0) ? 1 : 0;
+    int t2 = (nd == 3) ? ((dir == 2) ? 1 : 2) : -1;
+    int lt, a1, a2 = 0;
+    if (nd == 3) { lt = pt / 4; a1 = (pt / 2) % 2; a2 = pt % 2; }
+    else { lt = pt / 2; a1 = pt % 2; }
+    x[0] = x[1] = x[2] = 0.0;
+    x[dir] = side ? 0.5 : -0.5;
+    x[t1] = a1 ? g : -g;
+    if (t2 >= 0) x[t2] = a2 ? g : -g;
+    *tau = 0.5 + (lt ? g : -g);
+}
+
+/* Reconstruction + predictor of one zone from the padded array.  With the
+ * positivity option, a zone whose predictor met an inadmissible state at any
+ * quadrature node, or whose final polynomial is inadmissible at any face
+ * point, falls back to its zone mean (first order in space and time).
+ * Returns 1 for such a zone. */
+static int zone_q(const ocfg *c, const grid_t *g, const double *P, const double *lam,
+                  int i, int j, int k, double *q)
 {
     double blk[MAXV * 125], W[MAXST * MAXV];
+    int nd = g->nd, nv = g->nv;
     gather_block(g, P, i, j, k, blk);
     oracle_recon_block(c, blk, W);
-    oracle_predict(c, lam, W, q);
+    int bad = oracle_predict(c, lam, W, q);
+    if (!c->positivity) return 0;
+    mode4 m[MAXST];
+    int nst = st_modes(nd, c->order - 1, m);
+    int npt = (nd == 3) ? 8 : 4;
+    for (int dir = 0; dir < nd && !bad; ++dir)
+        for (int side = 0; side < 2 && !bad; ++side)
+            for (int pt = 0; pt < npt && !bad; ++pt) {
+                double x[3], tau, U[MAXV];
+                face_point(nd, dir, side, pt, x, &tau);
+                eval_modes(nv, nst, m, q, x[0], x[1], x[2], tau, U);
+                if (!admissible(c, U)) bad = 1;
+            }
+    if (!bad) return 0;
+    int nzb = (nd == 3) ? 5 : 1;
+    int centre = (nd == 3) ? (2 * 5 + 2) * 5 + 2 : 2 * 5 + 2;
+    for (int t = 0; t < nst * nv; ++t) q[t] = 0.0;
+    for (int v = 0; v < nv; ++v) q[v] = blk[v * nzb * 25 + centre];
+    return 1;
 }
 
 /* Face flux between zone qa (left, lower index) and qb (right) along dir:
@@ -600,7 +653,16 @@ double oracle_cfl_dt(const ocfg *c, const double *U, long long *bad)
 
 /* One ADER-WENO step of the whole grid with time step dt.  U, Unew: interior
  * SoA [nv][nz][ny][nx] (may not alias).  Returns 0, or -1 on allocation failure. */
+int oracle_step_count(const ocfg *c, const double *U, double dt, double *Unew, long long *ntroubled);
 int oracle_step(const ocfg *c, const double *U, double dt, double *Unew)
+{
+    long long n;
+    return oracle_step_count(c, U, dt, Unew, &n);
+}
+
+/* One step; *ntroubled receives the number of zones of the predictor box
+ * (interior grown by one zone per active axis) that used the fallback. */
+int oracle_step_count(const ocfg *c, const double *U, double dt, double *Unew, long long *ntroubled)
 {
     grid_t g;
     grid_init(c, &g);
@@ -618,11 +680,13 @@ int oracle_step(const ocfg *c, const double *U, double dt, double *Unew)
     double *Q = (double *)malloc(sizeof(double) * ne * qs);
     if (!Q) { free(P); return -1; }
     int o3 = (nd == 3) ? 1 : 0;
-#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+    long long nbad = 0;
+#pragma omp parallel for schedule(dynamic, 1) collapse(2) reduction(+ : nbad)
     for (int k = 0; k < e[2]; ++k)
         for (int j = 0; j < e[1]; ++j)
             for (int i = 0; i < e[0]; ++i)
-                zone_q(c, &g, P, lam, i - 1, j - 1, k - o3, Q + (((size_t)k * e[1] + j) * e[0] + i) * qs);
+                nbad += zone_q(c, &g, P, lam, i - 1, j - 1, k - o3, Q + (((size_t)k * e[1] + j) * e[0] + i) * qs);
+    *ntroubled = nbad;
 #define QAT(i, j, k) (Q + (((size_t)((k) + o3) * e[1] + ((j) + 1)) * e[0] + ((i) + 1)) * qs)
     size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
 #pragma omp parallel for schedule(static) collapse(2)

@@ -1,0 +1,605 @@
+// hog.hip -- C ABI of the gfx950 ADER-WENO Euler zone update: workspace
+// planning, argument checks and the per-step launch sequence on the caller's
+// HIP stream.  The kernels are in hog_kernels.h.
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "hog.h"
+#include "hog_kernels.h"
+
+using namespace hog;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(HOG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Plan {
+    int nd, nv, p;
+    int n[3];
+    Pad pad;
+    Box I, AX, BY, R, FB[3];
+    int ms, mst;
+    // byte offsets in the workspace
+    size_t off_info, off_U[2], off_A, off_B, off_W, off_FP, off_F[3], off_Q, off_stage, total;
+};
+
+int nmodes(int d, int p) { int r = 1; for (int i = 1; i <= d; ++i) r = r * (p + i) / i; return r; }
+
+int check_cfg(const hog_config* c)
+{
+    if (!c) return fail(HOG_EINVAL, "config is NULL");
+    if (c->ndim != 2 && c->ndim != 3) return fail(HOG_EINVAL, "ndim must be 2 or 3 (got %d)", c->ndim);
+    if (c->order != 3 && c->order != 4) return fail(HOG_EINVAL, "order must be 3 or 4 (got %d)", c->order);
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(HOG_EINVAL, "zone counts must be >= 1");
+    if (c->ndim == 2 && c->nz != 1) return fail(HOG_EINVAL, "nz must be 1 in 2D");
+    if (c->riemann < 0 || c->riemann > 2) return fail(HOG_EINVAL, "unknown Riemann solver %d", c->riemann);
+    for (int d = 0; d < 3; ++d)
+        if (c->bc[d] != HOG_PERIODIC && c->bc[d] != HOG_OUTFLOW) return fail(HOG_EINVAL, "bad boundary type on axis %d", d);
+    if (c->precision != HOG_FP64) return fail(HOG_EINVAL, "precision %d not supported", c->precision);
+    for (int i = 0; i < 3; ++i)
+        if (c->reserved[i] != 0) return fail(HOG_EINVAL, "reserved fields must be 0");
+    if (c->positivity != 0 && c->positivity != 1) return fail(HOG_EINVAL, "positivity must be 0 or 1");
+    if (!(c->gamma > 1.0) || !std::isfinite(c->gamma)) return fail(HOG_EINVAL, "gamma must be > 1");
+    const double h[3] = {c->dx, c->dy, c->dz};
+    for (int d = 0; d < c->ndim; ++d)
+        if (!(h[d] > 0.0) || !std::isfinite(h[d])) return fail(HOG_EINVAL, "zone width on axis %d must be > 0", d);
+    if (!(c->cfl > 0.0) || !(c->cfl <= 1.0)) return fail(HOG_EINVAL, "cfl must be in (0, 1]");
+    // periodic wrap of a 5-zone stencil plus one face neighbour needs n >= 3 on periodic axes
+    const int n[3] = {c->nx, c->ny, c->nz};
+    for (int d = 0; d < c->ndim; ++d)
+        if (c->bc[d] == HOG_PERIODIC && n[d] < 3) return fail(HOG_EINVAL, "periodic axis %d needs >= 3 zones", d);
+    long long N = (long long)c->nx * c->ny * c->nz;
+    if (N > (1ll << 31)) return fail(HOG_EINVAL, "too many zones (%lld)", N);
+    return HOG_OK;
+}
+
+Box make_box(int l0, int l1, int l2, int n0, int n1, int n2)
+{
+    Box b;
+    b.lo[0] = l0; b.lo[1] = l1; b.lo[2] = l2;
+    b.n[0] = n0; b.n[1] = n1; b.n[2] = n2;
+    return b;
+}
+
+void plan(const hog_config* c, Plan* P)
+{
+    const int nd = c->ndim, p = c->order - 1, nv = nd + 2;
+    P->nd = nd; P->nv = nv; P->p = p;
+    P->n[0] = c->nx; P->n[1] = c->ny; P->n[2] = (nd == 3) ? c->nz : 1;
+    const int g3 = (nd == 3) ? kGhostZones : 0;
+    P->pad.np[0] = P->n[0] + 2 * kGhostZones;
+    P->pad.np[1] = P->n[1] + 2 * kGhostZones;
+    P->pad.np[2] = P->n[2] + 2 * g3;
+    P->pad.off[0] = kGhostZones; P->pad.off[1] = kGhostZones; P->pad.off[2] = g3;
+    P->pad.vs = (long long)P->pad.np[0] * P->pad.np[1] * P->pad.np[2];
+    const int nx = P->n[0], ny = P->n[1], nz = P->n[2];
+    P->I = make_box(0, 0, 0, nx, ny, nz);
+    if (nd == 3) {
+        P->AX = make_box(-1, -3, -3, nx + 2, ny + 6, nz + 6);
+        P->BY = make_box(-1, -1, -3, nx + 2, ny + 2, nz + 6);
+        P->R = make_box(-1, -1, -1, nx + 2, ny + 2, nz + 2);
+        P->FB[2] = make_box(0, 0, -1, nx, ny, nz + 1);
+    } else {
+        P->AX = make_box(-1, -3, 0, nx + 2, ny + 6, 1);
+        P->BY = make_box(-1, -1, 0, nx + 2, ny + 2, 1);
+        P->R = P->BY;
+        P->FB[2] = make_box(0, 0, 0, 0, 0, 0);
+    }
+    P->FB[0] = make_box(-1, 0, 0, nx + 1, ny, nz);
+    P->FB[1] = make_box(0, -1, 0, nx, ny + 1, nz);
+    P->ms = nmodes(nd, p);
+    P->mst = nmodes(nd + 1, p);
+    const int npairs = (p + 1) * (p + 2) / 2;
+    const int npt = 1 << nd;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    P->off_info = take(sizeof(StepInfo));
+    P->off_U[0] = take(sizeof(double) * nv * P->pad.vs);
+    P->off_U[1] = take(sizeof(double) * nv * P->pad.vs);
+    P->off_A = take(sizeof(double) * (p + 1) * nv * box_size(P->AX));
+    P->off_B = take(sizeof(double) * npairs * nv * box_size(P->BY));
+    P->off_W = (nd == 3) ? take(sizeof(double) * P->ms * nv * box_size(P->R)) : P->off_B;
+    P->off_FP = take(sizeof(double) * nd * 2 * npt * nv * box_size(P->R));
+    for (int d = 0; d < 3; ++d) P->off_F[d] = (d < nd) ? take(sizeof(double) * nv * box_size(P->FB[d])) : 0;
+    P->off_Q = c->debug ? take(sizeof(double) * P->mst * nv * box_size(P->R)) : 0;
+    P->off_stage = take(sizeof(double) * nv * box_size(P->I));
+    P->total = o;
+}
+
+} // namespace
+
+struct hog_grid {
+    hog_config cfg;
+    Plan P;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    int cur;
+    bool have_state, have_step, smax_valid;
+    long long last_bad;
+    WenoArgs wa;
+    double h[3];
+    StepInfo* info;
+    double* U[2];
+    double *A, *B, *W, *FP, *F[3], *Q, *stage;
+    // stage timing: pairs of events per recorded stage launch, evaluated on read
+    bool profiling;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+};
+
+namespace {
+
+inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipEvent_t take_event(hog_grid* g)
+{
+    if (!g->ev_pool.empty()) {
+        hipEvent_t e = g->ev_pool.back();
+        g->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// RAII marker: records a start event now and an end event when it goes out
+// of scope, both on the handle's stream, if profiling is on.
+struct StageMark {
+    hog_grid* g;
+    int stage;
+    hipEvent_t a = nullptr, b = nullptr;
+    StageMark(hog_grid* g_, int s) : g(g_), stage(s)
+    {
+        if (!g->profiling) return;
+        a = take_event(g);
+        b = take_event(g);
+        if (a && b) (void)hipEventRecord(a, g->stream);
+    }
+    ~StageMark()
+    {
+        if (!g->profiling || !a || !b) return;
+        (void)hipEventRecord(b, g->stream);
+        g->ev_used.push_back({stage, {a, b}});
+    }
+};
+
+int launch_check(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(HOG_EDEVICE, "launch of %s failed: %s", what, hipGetErrorString(e));
+    return HOG_OK;
+}
+
+template <int D, int P>
+int enqueue_step_t(hog_grid* g, double dt_user)
+{
+    const Plan& L = g->P;
+    hipStream_t s = g->stream;
+    const double* h = g->h;
+    double* Uc = g->U[g->cur];
+    double* Un = g->U[g->cur ^ 1];
+    k_begin_step<<<1, 1, 0, s>>>(g->info, dt_user, g->cfg.cfl, h[0], h[1], h[2]);
+    {
+        StageMark m(g, 0);
+        const long long npad = (long long)L.pad.np[0] * L.pad.np[1] * L.pad.np[2];
+        k_ghost<D><<<nblocks(npad, 256), 256, 0, s>>>(Uc, L.pad, L.n[0], L.n[1], L.n[2], g->cfg.bc[0],
+                                                       g->cfg.bc[1], g->cfg.bc[2]);
+    }
+    {
+        StageMark m(g, 1);
+        k_recon_x<D, P><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, g->A, g->wa);
+        k_recon_y<D, P><<<nblocks(box_size(L.BY), 256), 256, 0, s>>>(g->A, L.AX, L.BY, g->B, g->wa);
+        if constexpr (D == 3)
+            k_recon_z<P><<<nblocks(box_size(L.R), 256), 256, 0, s>>>(g->B, L.BY, L.R, g->W, g->wa);
+    }
+    {
+        StageMark m(g, 2);
+        using S = PredShape<D, P>;
+        k_predict<D, P><<<nblocks(box_size(L.R), S::ZPW), 64, 0, s>>>(g->W, L.R, g->info, g->cfg.gamma,
+                                                                       g->cfg.positivity, g->FP, g->Q);
+    }
+    {
+        StageMark m(g, 3);
+        for (int d = 0; d < D; ++d)
+            k_riemann<D><<<nblocks(box_size(L.FB[d]), 256), 256, 0, s>>>(g->FP, L.R, L.FB[d], d, g->cfg.riemann,
+                                                                          g->cfg.gamma, g->F[d]);
+    }
+    {
+        StageMark m(g, 4);
+        k_update<D><<<nblocks(box_size(L.I), 256), 256, 0, s>>>(Uc, Un, L.pad, L.I, g->F[0], L.FB[0], g->F[1],
+                                                               L.FB[1], g->F[2], L.FB[2], g->info, g->cfg.gamma,
+                                                               1.0 / h[0], 1.0 / h[1], 1.0 / h[2]);
+    }
+    return launch_check("step");
+}
+
+int enqueue_step(hog_grid* g, double dt_user)
+{
+    const int key = g->P.nd * 10 + g->P.p;
+    switch (key) {
+    case 22: return enqueue_step_t<2, 2>(g, dt_user);
+    case 23: return enqueue_step_t<2, 3>(g, dt_user);
+    case 32: return enqueue_step_t<3, 2>(g, dt_user);
+    case 33: return enqueue_step_t<3, 3>(g, dt_user);
+    }
+    return fail(HOG_EINVAL, "unsupported dimension/order");
+}
+
+int enqueue_cfl(hog_grid* g, int which)
+{
+    const Plan& L = g->P;
+    k_reset<<<1, 1, 0, g->stream>>>(g->info, 0.0, 0);
+    if (L.nd == 3)
+        k_cfl<3><<<nblocks(box_size(L.I), 256), 256, 0, g->stream>>>(g->U[which], L.pad, L.I, g->info,
+                                                                      g->cfg.gamma, 1.0 / g->h[0], 1.0 / g->h[1],
+                                                                      1.0 / g->h[2]);
+    else
+        k_cfl<2><<<nblocks(box_size(L.I), 256), 256, 0, g->stream>>>(g->U[which], L.pad, L.I, g->info,
+                                                                      g->cfg.gamma, 1.0 / g->h[0], 1.0 / g->h[1],
+                                                                      1.0 / g->h[2]);
+    return launch_check("cfl");
+}
+
+int read_info(hog_grid* g, StepInfo* out)
+{
+    HIP_TRY(hipMemcpyAsync(out, g->info, sizeof(StepInfo), hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return HOG_OK;
+}
+
+double smax_of(const StepInfo& si)
+{
+    double s;
+    std::memcpy(&s, &si.smax_bits, sizeof s);
+    return s;
+}
+
+} // namespace
+
+extern "C" {
+
+int hog_abi_version(void) { return HOG_ABI_VERSION; }
+
+const char* hog_last_error(void) { return g_err; }
+
+int hog_workspace_size(const hog_config* cfg, size_t* bytes)
+{
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (!bytes) return fail(HOG_EINVAL, "bytes is NULL");
+    Plan P;
+    plan(cfg, &P);
+    *bytes = P.total;
+    return HOG_OK;
+}
+
+int hog_create(const hog_config* cfg, void* workspace, size_t bytes, void* hip_stream, hog_grid** out)
+{
+    g_err[0] = 0;
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (!out) return fail(HOG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!workspace) return fail(HOG_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(HOG_EINVAL, "workspace must be 256-byte aligned");
+    Plan P;
+    plan(cfg, &P);
+    if (bytes < P.total) return fail(HOG_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, P.total);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(HOG_EDEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    hog_grid* g = new (std::nothrow) hog_grid();
+    if (!g) return fail(HOG_ENOMEM, "host allocation failed");
+    g->cfg = *cfg;
+    g->P = P;
+    g->stream = static_cast<hipStream_t>(hip_stream);
+    g->ws = static_cast<char*>(workspace);
+    g->ws_bytes = bytes;
+    g->cur = 0;
+    g->have_state = g->have_step = g->smax_valid = false;
+    g->profiling = false;
+    g->last_bad = -1;
+    g->h[0] = cfg->dx; g->h[1] = cfg->dy; g->h[2] = (P.nd == 3) ? cfg->dz : 1.0;
+    g->wa.eps = cfg->weno_eps > 0.0 ? cfg->weno_eps : 1e-12;
+    const bool g3zero = cfg->g3[0] == 0.0 && cfg->g3[1] == 0.0 && cfg->g3[2] == 0.0;
+    const bool g4zero = cfg->g4[0] == 0.0 && cfg->g4[1] == 0.0 && cfg->g4[2] == 0.0 && cfg->g4[3] == 0.0;
+    if (P.p == 2) {
+        const double d3[3] = {0.075, 0.85, 0.075};
+        for (int i = 0; i < 3; ++i) g->wa.g[i] = g3zero ? d3[i] : cfg->g3[i];
+        g->wa.g[3] = 0.0;
+    } else {
+        const double d4[4] = {0.85, 0.01125, 0.1275, 0.01125};
+        for (int i = 0; i < 4; ++i) g->wa.g[i] = g4zero ? d4[i] : cfg->g4[i];
+    }
+    g->wa.linear = cfg->linear_weno ? 1 : 0;
+    g->info = reinterpret_cast<StepInfo*>(g->ws + P.off_info);
+    g->U[0] = reinterpret_cast<double*>(g->ws + P.off_U[0]);
+    g->U[1] = reinterpret_cast<double*>(g->ws + P.off_U[1]);
+    g->A = reinterpret_cast<double*>(g->ws + P.off_A);
+    g->B = reinterpret_cast<double*>(g->ws + P.off_B);
+    g->W = reinterpret_cast<double*>(g->ws + P.off_W);
+    g->FP = reinterpret_cast<double*>(g->ws + P.off_FP);
+    for (int d = 0; d < 3; ++d) g->F[d] = (d < P.nd) ? reinterpret_cast<double*>(g->ws + P.off_F[d]) : nullptr;
+    g->Q = cfg->debug ? reinterpret_cast<double*>(g->ws + P.off_Q) : nullptr;
+    g->stage = reinterpret_cast<double*>(g->ws + P.off_stage);
+    k_reset<<<1, 1, 0, g->stream>>>(g->info, 0.0, 1);
+    rc = launch_check("reset");
+    if (rc) { delete g; return rc; }
+    *out = g;
+    return HOG_OK;
+}
+
+int hog_destroy(hog_grid* g)
+{
+    if (!g) return HOG_OK;
+    if (!g->ev_used.empty()) (void)hipStreamSynchronize(g->stream);
+    for (auto& u : g->ev_used) {
+        (void)hipEventDestroy(u.second.first);
+        (void)hipEventDestroy(u.second.second);
+    }
+    for (auto e : g->ev_pool) (void)hipEventDestroy(e);
+    delete g;
+    return HOG_OK;
+}
+
+int hog_profile_enable(hog_grid* g, int enable)
+{
+    if (!g) return fail(HOG_EINVAL, "NULL handle");
+    g->profiling = enable != 0;
+    return HOG_OK;
+}
+
+int hog_profile_read(hog_grid* g, double* ms, int* launches, int nstages)
+{
+    if (!g || !ms || !launches || nstages < HOG_NSTAGES) return fail(HOG_EINVAL, "bad arguments");
+    for (int i = 0; i < nstages; ++i) { ms[i] = 0.0; launches[i] = 0; }
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    for (auto& u : g->ev_used) {
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, u.second.first, u.second.second));
+        ms[u.first] += t;
+        launches[u.first] += 1;
+        g->ev_pool.push_back(u.second.first);
+        g->ev_pool.push_back(u.second.second);
+    }
+    g->ev_used.clear();
+    return HOG_OK;
+}
+
+int hog_set_state(hog_grid* g, const double* U, int layout, int where)
+{
+    if (!g || !U) return fail(HOG_EINVAL, "NULL argument");
+    if (layout != HOG_SOA && layout != HOG_AOS) return fail(HOG_EINVAL, "unknown layout %d", layout);
+    if (where != HOG_HOST && where != HOG_DEVICE) return fail(HOG_EINVAL, "unknown location %d", where);
+    const Plan& L = g->P;
+    const long long N = box_size(L.I);
+    const double* src = U;
+    if (where == HOG_HOST) {
+        HIP_TRY(hipMemcpyAsync(g->stage, U, sizeof(double) * L.nv * N, hipMemcpyHostToDevice, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+        src = g->stage;
+    }
+    const int aos = layout == HOG_AOS;
+    if (L.nd == 3) k_pack<3><<<nblocks(N, 256), 256, 0, g->stream>>>(src, g->U[g->cur], L.pad, L.I, aos);
+    else k_pack<2><<<nblocks(N, 256), 256, 0, g->stream>>>(src, g->U[g->cur], L.pad, L.I, aos);
+    int rc = launch_check("pack");
+    if (rc) return rc;
+    rc = enqueue_cfl(g, g->cur);
+    if (rc) return rc;
+    g->have_state = true;
+    g->smax_valid = true;
+    g->have_step = false;
+    return HOG_OK;
+}
+
+int hog_get_state(hog_grid* g, double* U, int layout, int where)
+{
+    if (!g || !U) return fail(HOG_EINVAL, "NULL argument");
+    if (layout != HOG_SOA && layout != HOG_AOS) return fail(HOG_EINVAL, "unknown layout %d", layout);
+    if (where != HOG_HOST && where != HOG_DEVICE) return fail(HOG_EINVAL, "unknown location %d", where);
+    if (!g->have_state) return fail(HOG_ESTATE, "no state set");
+    const Plan& L = g->P;
+    const long long N = box_size(L.I);
+    double* dst = (where == HOG_DEVICE) ? U : g->stage;
+    const int aos = layout == HOG_AOS;
+    if (L.nd == 3) k_unpack<3><<<nblocks(N, 256), 256, 0, g->stream>>>(g->U[g->cur], dst, L.pad, L.I, aos);
+    else k_unpack<2><<<nblocks(N, 256), 256, 0, g->stream>>>(g->U[g->cur], dst, L.pad, L.I, aos);
+    int rc = launch_check("unpack");
+    if (rc) return rc;
+    if (where == HOG_HOST) {
+        HIP_TRY(hipMemcpyAsync(U, g->stage, sizeof(double) * L.nv * N, hipMemcpyDeviceToHost, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+    }
+    return HOG_OK;
+}
+
+int hog_compute_dt(hog_grid* g, double* dt)
+{
+    if (!g || !dt) return fail(HOG_EINVAL, "NULL argument");
+    if (!g->have_state) return fail(HOG_ESTATE, "no state set");
+    int rc;
+    if (!g->smax_valid) {
+        rc = enqueue_cfl(g, g->cur);
+        if (rc) return rc;
+        g->smax_valid = true;
+    }
+    StepInfo si;
+    rc = read_info(g, &si);
+    if (rc) return rc;
+    if (si.bad != ULLONG_MAX) {
+        g->last_bad = (long long)si.bad;
+        return fail(HOG_ENONPHYS, "non-physical state in zone %lld", g->last_bad);
+    }
+    g->last_bad = -1;
+    *dt = g->cfg.cfl / smax_of(si);
+    return HOG_OK;
+}
+
+int hog_step(hog_grid* g, double dt, double* dt_next)
+{
+    if (!g) return fail(HOG_EINVAL, "NULL handle");
+    if (!g->have_state) return fail(HOG_ESTATE, "no state set");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HOG_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+    int rc = enqueue_step(g, dt);
+    if (rc) return rc;
+    g->have_step = true;
+    if (!dt_next) {
+        g->cur ^= 1;
+        g->smax_valid = true;
+        return HOG_OK;
+    }
+    StepInfo si;
+    rc = read_info(g, &si);
+    if (rc) return rc;
+    if (si.bad != ULLONG_MAX) {
+        g->last_bad = (long long)si.bad;
+        // keep the pre-step state; its CFL reduction is recomputed on demand
+        g->smax_valid = false;
+        return fail(HOG_ENONPHYS, "step produced a non-physical state in zone %lld", g->last_bad);
+    }
+    g->last_bad = -1;
+    g->cur ^= 1;
+    g->smax_valid = true;
+    *dt_next = g->cfg.cfl / smax_of(si);
+    return HOG_OK;
+}
+
+int hog_advance(hog_grid* g, int nsteps, double t_end, double* t_out)
+{
+    if (!g) return fail(HOG_EINVAL, "NULL handle");
+    if (!g->have_state) return fail(HOG_ESTATE, "no state set");
+    if (nsteps < 0 || !std::isfinite(t_end)) return fail(HOG_EINVAL, "bad nsteps / t_end");
+    int rc;
+    if (!g->smax_valid) {
+        rc = enqueue_cfl(g, g->cur);
+        if (rc) return rc;
+        g->smax_valid = true;
+    }
+    // reset the time accumulator without touching the CFL reduction
+    {
+        StepInfo si;
+        rc = read_info(g, &si);
+        if (rc) return rc;
+        if (si.bad != ULLONG_MAX) {
+            g->last_bad = (long long)si.bad;
+            return fail(HOG_ENONPHYS, "non-physical state in zone %lld", g->last_bad);
+        }
+        si.t = 0.0;
+        si.t_end = t_end > 0.0 ? t_end : 0.0;
+        HIP_TRY(hipMemcpyAsync(g->info, &si, sizeof si, hipMemcpyHostToDevice, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+    }
+    double t = 0.0;
+    for (int s = 0; s < nsteps; ++s) {
+        rc = enqueue_step(g, -1.0);
+        if (rc) return rc;
+        g->cur ^= 1;
+        g->have_step = true;
+        if (t_end > 0.0) {
+            StepInfo si;
+            rc = read_info(g, &si);
+            if (rc) return rc;
+            t = si.t;
+            if (si.bad != ULLONG_MAX) {
+                g->last_bad = (long long)si.bad;
+                return fail(HOG_ENONPHYS, "non-physical state in zone %lld", g->last_bad);
+            }
+            if (t >= t_end * (1.0 - 1e-14) || si.dt <= 0.0) break;
+        }
+    }
+    StepInfo si;
+    rc = read_info(g, &si);
+    if (rc) return rc;
+    if (si.bad != ULLONG_MAX) {
+        g->last_bad = (long long)si.bad;
+        return fail(HOG_ENONPHYS, "non-physical state in zone %lld", g->last_bad);
+    }
+    g->last_bad = -1;
+    if (t_out) *t_out = si.t;
+    return HOG_OK;
+}
+
+long long hog_last_bad_zone(hog_grid* g) { return g ? g->last_bad : -1; }
+
+int hog_stats(hog_grid* g, double* t, double* dt, long long* fallback_zones)
+{
+    if (!g) return fail(HOG_EINVAL, "NULL handle");
+    StepInfo si;
+    int rc = read_info(g, &si);
+    if (rc) return rc;
+    if (t) *t = si.t;
+    if (dt) *dt = si.dt;
+    if (fallback_zones) *fallback_zones = (long long)si.fallback;
+    return HOG_OK;
+}
+
+int hog_debug_tap(hog_grid* g, int tap, void* dst, size_t bytes)
+{
+    if (!g || !dst) return fail(HOG_EINVAL, "NULL argument");
+    if (!g->have_step) return fail(HOG_ESTATE, "no step taken yet");
+    const Plan& L = g->P;
+    const long long N = box_size(L.I), nR = box_size(L.R);
+    const int nv = L.nv;
+    if (tap == HOG_TAP_MODES || tap == HOG_TAP_STMODES) {
+        const int nm = (tap == HOG_TAP_MODES) ? L.ms : L.mst;
+        const double* src = (tap == HOG_TAP_MODES) ? g->W : g->Q;
+        if (!src) return fail(HOG_EINVAL, "space-time modes are kept only with debug = 1");
+        if (bytes < sizeof(double) * N * nm * nv) return fail(HOG_EINVAL, "tap buffer too small");
+        std::vector<double> h((size_t)nm * nv * nR);
+        HIP_TRY(hipMemcpyAsync(h.data(), src, sizeof(double) * h.size(), hipMemcpyDeviceToHost, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+        double* out = static_cast<double*>(dst);
+        for (int k = 0; k < L.n[2]; ++k)
+            for (int j = 0; j < L.n[1]; ++j)
+                for (int i = 0; i < L.n[0]; ++i) {
+                    const long long z = ((long long)k * L.n[1] + j) * L.n[0] + i;
+                    const long long r = ((long long)(k - L.R.lo[2]) * L.R.n[1] + (j - L.R.lo[1])) * L.R.n[0] +
+                                        (i - L.R.lo[0]);
+                    for (int m = 0; m < nm; ++m)
+                        for (int v = 0; v < nv; ++v) out[(z * nm + m) * nv + v] = h[((size_t)m * nv + v) * nR + r];
+                }
+        return HOG_OK;
+    }
+    if (tap >= HOG_TAP_FLUX_X && tap <= HOG_TAP_FLUX_Z) {
+        const int d = tap - HOG_TAP_FLUX_X;
+        if (d >= L.nd) return fail(HOG_EINVAL, "no z faces in 2D");
+        const long long nF = box_size(L.FB[d]);
+        if (bytes < sizeof(double) * nv * nF) return fail(HOG_EINVAL, "tap buffer too small");
+        HIP_TRY(hipMemcpyAsync(dst, g->F[d], sizeof(double) * nv * nF, hipMemcpyDeviceToHost, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+        return HOG_OK;
+    }
+    return fail(HOG_EINVAL, "unknown tap %d", tap);
+}
+
+} // extern "C"

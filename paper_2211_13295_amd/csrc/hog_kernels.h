@@ -1,0 +1,753 @@
+// hog_kernels.h -- gfx950 kernels of the ADER-WENO zone update (FP64 path).
+//
+// Data layout in HBM (all structure-of-arrays, x fastest, one array per
+// (mode, variable) so consecutive lanes touch consecutive zones):
+//   U[2]  padded state, ghost width 3 on every active axis (double buffer);
+//   A     x-sweep output   [a][v]        over box AX = x:[-1,n] y:[-3,n+2] z:[-3,n+2]
+//   B     y-sweep output   [(a,b)][v]    over box BY = x:[-1,n] y:[-1,n]   z:[-3,n+2]
+//   W     spatial modes    [m][v]        over box R  = x:[-1,n] y:[-1,n]   z:[-1,n]
+//                          (in 2D the y-sweep output is W)
+//   FP    face-point states [d][side][pt][v] over R (predictor output)
+//   F[d]  face fluxes [v] over the faces f+1/2, f in [-1, n-1] along d
+// Boxes use interior zone numbering (0..n-1 are interior zones).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <climits>
+#include "hog_tables.h"
+#include "hog_physics.h"
+
+namespace hog {
+
+constexpr int kGhostZones = 3;   // WENO radius 2 plus one face neighbour
+
+struct Box {
+    int lo[3];
+    int n[3];
+};
+struct Pad {
+    int np[3];
+    int off[3];
+    long long vs;   // stride between variables
+};
+
+__host__ __device__ inline long long box_size(const Box& b) { return (long long)b.n[0] * b.n[1] * b.n[2]; }
+__device__ __forceinline__ void box_ijk(const Box& b, long long idx, int& i, int& j, int& k)
+{
+    i = (int)(idx % b.n[0]) + b.lo[0];
+    long long r = idx / b.n[0];
+    j = (int)(r % b.n[1]) + b.lo[1];
+    k = (int)(r / b.n[1]) + b.lo[2];
+}
+__device__ __forceinline__ long long box_index(const Box& b, int i, int j, int k)
+{
+    return ((long long)(k - b.lo[2]) * b.n[1] + (j - b.lo[1])) * b.n[0] + (i - b.lo[0]);
+}
+__device__ __forceinline__ long long pad_index(const Pad& p, int i, int j, int k)
+{
+    return ((long long)(k + p.off[2]) * p.np[1] + (j + p.off[1])) * p.np[0] + (i + p.off[0]);
+}
+
+// Per-step scalars kept on the device so a run of steps needs no host round trip.
+struct StepInfo {
+    double dt;                      // time step of the current step
+    double t;                       // time advanced since the last reset
+    double t_end;                   // > 0: clip dt so that t does not pass t_end
+    double lam[3];                  // dt / dx_d
+    unsigned long long smax_bits;   // bits of max_zones sum_d (|u_d| + c) / dx_d (>= 0)
+    unsigned long long bad;         // first non-physical zone, ULLONG_MAX if none
+    unsigned long long fallback;    // predictor zones that used the positivity fallback
+    double pad_[7];
+};
+
+// ------------------------------------------------------------------------
+// Step bookkeeping
+// ------------------------------------------------------------------------
+__global__ void k_begin_step(StepInfo* info, double dt_user, double cfl, double h0, double h1, double h2)
+{
+    double dt = dt_user;
+    if (!(dt > 0.0)) dt = cfl / __longlong_as_double((long long)info->smax_bits);
+    if (info->t_end > 0.0) {
+        double rem = info->t_end - info->t;
+        if (dt > rem) dt = rem > 0.0 ? rem : 0.0;
+    }
+    info->dt = dt;
+    info->lam[0] = dt / h0;
+    info->lam[1] = dt / h1;
+    info->lam[2] = dt / h2;
+    info->t += dt;
+    info->smax_bits = 0ull;
+    info->bad = ULLONG_MAX;
+    info->fallback = 0ull;
+}
+
+__global__ void k_reset(StepInfo* info, double t_end, int reset_time)
+{
+    if (reset_time) { info->t = 0.0; info->t_end = t_end; }
+    info->smax_bits = 0ull;
+    info->bad = ULLONG_MAX;
+}
+
+// ------------------------------------------------------------------------
+// a1: ghost zones (periodic wrap or zero-gradient clamp per axis; fills
+// edges and corners too).  One thread per padded zone; interior threads exit.
+// ------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_ghost(double* __restrict__ U, Pad p, int n0, int n1, int n2,
+                                               int bc0, int bc1, int bc2)
+{
+    constexpr int NV = D + 2;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tot = (long long)p.np[0] * p.np[1] * p.np[2];
+    if (idx >= tot) return;
+    int i = (int)(idx % p.np[0]) - p.off[0];
+    long long r = idx / p.np[0];
+    int j = (int)(r % p.np[1]) - p.off[1];
+    int k = (int)(r / p.np[1]) - p.off[2];
+    const bool inside = i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2;
+    if (inside) return;
+    auto src = [](int x, int n, int bc) {
+        if (bc == 0) { x %= n; return x < 0 ? x + n : x; }
+        return x < 0 ? 0 : (x >= n ? n - 1 : x);
+    };
+    const int si = src(i, n0, bc0), sj = src(j, n1, bc1), sk = (D == 3) ? src(k, n2, bc2) : 0;
+    const long long s = pad_index(p, si, sj, sk);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U[v * p.vs + idx] = U[v * p.vs + s];
+}
+
+// ------------------------------------------------------------------------
+// a7: CFL signal speed and non-physical check of a state (block max, then
+// one 64-bit atomic max on the bit pattern: exact, hence deterministic).
+// ------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void cfl_reduce(double s, bool ok, long long zone, StepInfo* info)
+{
+    __shared__ double red[4];
+    if (!ok) atomicMin(&info->bad, (unsigned long long)zone);
+    double m = ok ? s : 0.0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) b = fmax(b, red[q]);
+        atomicMax(&info->smax_bits, (unsigned long long)__double_as_longlong(b));
+    }
+}
+
+template <int D>
+__device__ __forceinline__ double signal_speed(const double* u, double gamma, double ih0, double ih1, double ih2,
+                                               bool& ok)
+{
+    const double rho = u[0];
+    const double ir = 1.0 / rho;
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) ke += u[1 + d] * u[1 + d];
+    const double p = (gamma - 1.0) * (u[D + 1] - 0.5 * ke * ir);
+    ok = rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p);
+    const double c = sqrt(gamma * p * ir);
+    const double ih[3] = {ih0, ih1, ih2};
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) s += (fabs(u[1 + d] * ir) + c) * ih[d];
+    return s;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_cfl(const double* __restrict__ U, Pad p, Box I, StepInfo* info,
+                                             double gamma, double ih0, double ih1, double ih2)
+{
+    constexpr int NV = D + 2;
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    bool ok = true;
+    if (z < box_size(I)) {
+        int i, j, k;
+        box_ijk(I, z, i, j, k);
+        const long long pi = pad_index(p, i, j, k);
+        double u[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = U[v * p.vs + pi];
+        s = signal_speed<D>(u, gamma, ih0, ih1, ih2, ok);
+    }
+    cfl_reduce<D>(s, ok, z, info);
+}
+
+// ------------------------------------------------------------------------
+// a2: WENO reconstruction by successive 1D sweeps x -> y -> z.
+// ------------------------------------------------------------------------
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_recon_x(const double* __restrict__ U, Pad p, Box AX,
+                                                 double* __restrict__ A, WenoArgs wa)
+{
+    constexpr int NV = D + 2;
+    const long long nA = box_size(AX);
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= nA) return;
+    int i, j, k;
+    box_ijk(AX, z, i, j, k);
+    const long long base = pad_index(p, i, j, k);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double line[5], c[P + 1];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) line[o] = U[v * p.vs + base + (o - 2)];
+        weno1d<P>(line, c, wa);
+        A[(0 * NV + v) * nA + z] = line[2];
+#pragma unroll
+        for (int a = 1; a <= P; ++a) A[(a * NV + v) * nA + z] = c[a];
+    }
+}
+
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_recon_y(const double* __restrict__ A, Box AX, Box BY,
+                                                 double* __restrict__ B, WenoArgs wa)
+{
+    constexpr int NV = D + 2;
+    constexpr Pairs<P> PR{};
+    const long long nA = box_size(AX), nB = box_size(BY);
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= nB) return;
+    int i, j, k;
+    box_ijk(BY, z, i, j, k);
+    const long long c0 = box_index(AX, i, j, k);
+    const long long sy = AX.n[0];
+#pragma unroll
+    for (int a = 0; a <= P; ++a)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double line[5], c[P + 1];
+#pragma unroll
+            for (int o = 0; o < 5; ++o) line[o] = A[(a * NV + v) * nA + c0 + (o - 2) * sy];
+            B[(PR.at[a][0] * NV + v) * nB + z] = line[2];
+            if (P - a >= 1) {
+                weno1d<P>(line, c, wa);
+#pragma unroll
+                for (int b = 1; b <= P - a; ++b) B[(PR.at[a][b] * NV + v) * nB + z] = c[b];
+            }
+        }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_recon_z(const double* __restrict__ B, Box BY, Box R,
+                                                 double* __restrict__ W, WenoArgs wa)
+{
+    constexpr int NV = 5;
+    constexpr Modes<3, P> M{};
+    constexpr Pairs<P> PR{};
+    const long long nB = box_size(BY), nR = box_size(R);
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= nR) return;
+    int i, j, k;
+    box_ijk(R, z, i, j, k);
+    const long long c0 = box_index(BY, i, j, k);
+    const long long sz = (long long)BY.n[0] * BY.n[1];
+#pragma unroll
+    for (int b = 0; b <= P; ++b)
+#pragma unroll
+        for (int a = 0; a + b <= P; ++a)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double line[5], c[P + 1];
+#pragma unroll
+                for (int o = 0; o < 5; ++o) line[o] = B[(PR.at[a][b] * NV + v) * nB + c0 + (o - 2) * sz];
+                W[(M.at[a][b][0][0] * NV + v) * nR + z] = line[2];
+                if (P - a - b >= 1) {
+                    weno1d<P>(line, c, wa);
+#pragma unroll
+                    for (int cc = 1; cc <= P - a - b; ++cc) W[(M.at[a][b][cc][0] * NV + v) * nR + z] = c[cc];
+                }
+            }
+}
+
+// ------------------------------------------------------------------------
+// a4: ADER predictor.  One wavefront per zone group: lane = (zone slot,
+// spatial Gauss node).  Per Picard iteration each lane evaluates q at its
+// node for every time node, forms the physical fluxes and contracts them
+// against the time basis; the spatial L2 projection is then done as a
+// sum-factorised x -> y -> z transform in LDS, one flux direction at a time,
+// and the derivative / time-integral maps add the result into the new
+// space-time modes.  After the last iteration the face-point states needed
+// by the Riemann solver are evaluated from the final modes.
+// ------------------------------------------------------------------------
+template <int D, int P>
+struct PredShape {
+    static constexpr int NV = D + 2;
+    static constexpr int N1 = P + 1;
+    static constexpr int NS = ipow_c(N1, D);         // spatial nodes per zone
+    static constexpr int ZPW = 64 / NS;              // zones per wavefront
+    static constexpr int MS = Modes<D, P>::NS;
+    static constexpr int MST = Modes<D, P>::NST;
+    static constexpr int MT = MST - MS;              // modes with e >= 1
+    static constexpr int NE = P;                     // flux time modes feeding a derivative
+    static constexpr int SL = NE * NV * NS;          // LDS slice doubles per zone
+    static constexpr int NPT = 1 << D;               // Gauss points per face (tangential x time)
+    static constexpr int NFPZ = D * 2 * NPT;         // face points per zone
+    static constexpr int NTGT = ZPW * MT * NV;       // new-mode targets per wavefront
+    static constexpr int TPL = (NTGT + 63) / 64;     // targets per lane
+    static constexpr int MAXE = P * P;               // max source terms per target and axis
+};
+
+// For each axis d and target mode (e >= 1) the list of source flux modes:
+//  q[a..d..,e] -= lam_d * sum_{a'' > a_d, e'} D[a''][a_d] * I[e'][e] * f_d[.., a'' .., e']
+template <int D, int P>
+struct AsmTable {
+    using S = PredShape<D, P>;
+    int n[D][S::MT];
+    int off[D][S::MT][S::MAXE];     // LDS offset of the source, variable 0
+    int ep[D][S::MT][S::MAXE];      // its flux time mode e'
+    double coef[D][S::MT][S::MAXE];
+    constexpr AsmTable() : n{}, off{}, ep{}, coef{}
+    {
+        constexpr Modes<D, P> M{};
+        constexpr Rules<P> R{};
+        for (int d = 0; d < D; ++d)
+            for (int t = 0; t < S::MT; ++t) {
+                const int m = S::MS + t;
+                int tgt[3] = {M.a[m], M.b[m], M.c[m]};
+                const int e = M.e[m];
+                int cnt = 0;
+                for (int hi = tgt[d] + 1; hi <= P; ++hi)
+                    for (int epr = (e >= 1 ? e - 1 : 0); epr < S::NE; ++epr) {
+                        int src[3] = {tgt[0], tgt[1], tgt[2]};
+                        src[d] = hi;
+                        if (src[0] + src[1] + src[2] + epr > P) continue;
+                        const double cf = R.D[hi][tgt[d]] * R.I[epr][e];
+                        if (cf == 0.0) continue;
+                        const int spatial = (D == 3) ? (src[2] * S::N1 + src[1]) * S::N1 + src[0]
+                                                     : src[1] * S::N1 + src[0];
+                        off[d][t][cnt] = epr * S::NV * S::NS + spatial;
+                        ep[d][t][cnt] = epr;
+                        coef[d][t][cnt] = cf;
+                        ++cnt;
+                    }
+                n[d][t] = cnt;
+            }
+    }
+};
+
+__constant__ AsmTable<2, 2> c_asm22 = AsmTable<2, 2>();
+__constant__ AsmTable<2, 3> c_asm23 = AsmTable<2, 3>();
+__constant__ AsmTable<3, 2> c_asm32 = AsmTable<3, 2>();
+__constant__ AsmTable<3, 3> c_asm33 = AsmTable<3, 3>();
+
+template <int D, int P>
+__device__ __forceinline__ const AsmTable<D, P>& asm_table();
+template <> __device__ __forceinline__ const AsmTable<2, 2>& asm_table<2, 2>() { return c_asm22; }
+template <> __device__ __forceinline__ const AsmTable<2, 3>& asm_table<2, 3>() { return c_asm23; }
+template <> __device__ __forceinline__ const AsmTable<3, 2>& asm_table<3, 2>() { return c_asm32; }
+template <> __device__ __forceinline__ const AsmTable<3, 3>& asm_table<3, 3>() { return c_asm33; }
+
+template <int D, int P>
+__global__ __launch_bounds__(64) void k_predict(const double* __restrict__ W, Box R,
+                                                StepInfo* __restrict__ info, double gamma, int positivity,
+                                                double* __restrict__ FP, double* __restrict__ Qout)
+{
+    using S = PredShape<D, P>;
+    constexpr int NV = S::NV, N1 = S::N1, NS = S::NS, ZPW = S::ZPW;
+    constexpr int MS = S::MS, MST = S::MST, MT = S::MT, NE = S::NE, SL = S::SL;
+    constexpr Modes<D, P> M{};
+    constexpr Rules<P> RL{};
+    const AsmTable<D, P>& AT = asm_table<D, P>();
+
+    __shared__ double sq[ZPW * MST * NV];
+    __shared__ double sr[ZPW * SL];
+    __shared__ int sbad[ZPW];
+
+    const long long nR = box_size(R);
+    const int lane = threadIdx.x;
+    const long long zbase = (long long)blockIdx.x * ZPW;
+    const double gm1 = gamma - 1.0;
+    const double lam[3] = {info->lam[0], info->lam[1], info->lam[2]};
+
+    for (int t = lane; t < ZPW * MST * NV; t += 64) {
+        const int z = t / (MST * NV), r = t % (MST * NV), m = r / NV, v = r % NV;
+        const long long zone = zbase + z;
+        sq[t] = (m < MS && zone < nR) ? W[(long long)(m * NV + v) * nR + zone] : 0.0;
+    }
+    if (lane < ZPW) sbad[lane] = 0;
+
+    const int zs = lane / NS;
+    const int node = lane % NS;
+    const bool active = zs < ZPW;
+    const int ii = node % N1, jj = (node / N1) % N1, kk = (D == 3) ? node / (N1 * N1) : 0;
+    double px[P + 1], py[P + 1], pz[P + 1];
+    {
+        const double xn = gl_node(N1, ii), yn = gl_node(N1, jj), zn = gl_node(N1, kk);
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            px[a] = mleg(a, xn);
+            py[a] = mleg(a, yn);
+            pz[a] = (D == 3) ? mleg(a, zn) : (a == 0 ? 1.0 : 0.0);
+        }
+    }
+    __syncthreads();
+
+    for (int it = 0; it < P; ++it) {
+        const int ne = (it == 0) ? 1 : NE;   // first iterate is time-independent
+        double R[D][NE][NV];
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+#pragma unroll
+            for (int e = 0; e < NE; ++e)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) R[d][e][v] = 0.0;
+
+        if (active) {
+            double Qe[P + 1][NV];
+#pragma unroll
+            for (int e = 0; e <= P; ++e)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Qe[e][v] = 0.0;
+            const double* qz = sq + zs * MST * NV;
+#pragma unroll
+            for (int m = 0; m < MST; ++m) {
+                if (it == 0 && M.e[m] != 0) continue;
+                const double phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Qe[M.e[m]][v] += qz[m * NV + v] * phi;
+            }
+            bool ok = true;
+            if (it == 0) {
+                double F[D][NV];
+                ok = fluxes<D>(Qe[0], gm1, F);
+#pragma unroll
+                for (int d = 0; d < D; ++d)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) R[d][0][v] = F[d][v];
+            } else {
+#pragma unroll
+                for (int l = 0; l < N1; ++l) {
+                    double U[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        double s = Qe[P][v];
+#pragma unroll
+                        for (int e = P - 1; e >= 0; --e) s = s * RL.t[l] + Qe[e][v];
+                        U[v] = s;
+                    }
+                    double F[D][NV];
+                    ok = fluxes<D>(U, gm1, F) && ok;
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+#pragma unroll
+                        for (int e = 0; e < NE; ++e)
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) R[d][e][v] += RL.tproj[e][l] * F[d][v];
+                }
+            }
+            if (positivity && !ok) atomicOr(&sbad[zs], 1);
+        }
+
+        double acc[S::TPL];
+#pragma unroll
+        for (int r = 0; r < S::TPL; ++r) acc[r] = 0.0;
+
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int e = 0; e < NE; ++e)
+                    if (e < ne) {
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) sr[zs * SL + (e * NV + v) * NS + node] = R[d][e][v];
+                    }
+            }
+            __syncthreads();
+            // x: contract node index i -> a'
+            {
+                const int nl = ZPW * ne * NV * (NS / N1);
+                for (int l = lane; l < nl; l += 64) {
+                    const int z = l / (ne * NV * (NS / N1));
+                    const int rem = l % (ne * NV * (NS / N1));
+                    const int ev = rem / (NS / N1), row = rem % (NS / N1);
+                    double* s = sr + z * SL + ev * NS + row * N1;
+                    double x[N1], y[N1];
+#pragma unroll
+                    for (int i = 0; i < N1; ++i) x[i] = s[i];
+#pragma unroll
+                    for (int a = 0; a < N1; ++a) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int i = 0; i < N1; ++i) t += RL.proj[a][i] * x[i];
+                        y[a] = t;
+                    }
+#pragma unroll
+                    for (int a = 0; a < N1; ++a) s[a] = y[a];
+                }
+            }
+            __syncthreads();
+            // y: contract node index j -> b' (lines with a' <= P - e')
+            {
+                constexpr int NK = (D == 3) ? N1 : 1;
+                const int nl = ZPW * ne * NV * NK * N1;
+                for (int l = lane; l < nl; l += 64) {
+                    const int z = l / (ne * NV * NK * N1);
+                    int rem = l % (ne * NV * NK * N1);
+                    const int ev = rem / (NK * N1);
+                    rem %= (NK * N1);
+                    const int k = rem / N1, a = rem % N1;
+                    const int e = ev / NV;
+                    if (a > P - e) continue;
+                    double* s = sr + z * SL + ev * NS + k * N1 * N1 + a;
+                    double x[N1], y[N1];
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) x[j] = s[j * N1];
+#pragma unroll
+                    for (int b = 0; b < N1; ++b) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int j = 0; j < N1; ++j) t += RL.proj[b][j] * x[j];
+                        y[b] = t;
+                    }
+#pragma unroll
+                    for (int b = 0; b < N1; ++b) s[b * N1] = y[b];
+                }
+            }
+            __syncthreads();
+            if constexpr (D == 3) {
+                // z: contract node index k -> c' (lines with a' + b' <= P - e')
+                const int nl = ZPW * ne * NV * N1 * N1;
+                for (int l = lane; l < nl; l += 64) {
+                    const int z = l / (ne * NV * N1 * N1);
+                    int rem = l % (ne * NV * N1 * N1);
+                    const int ev = rem / (N1 * N1);
+                    rem %= (N1 * N1);
+                    const int b = rem / N1, a = rem % N1;
+                    const int e = ev / NV;
+                    if (a + b > P - e) continue;
+                    double* s = sr + z * SL + ev * NS + b * N1 + a;
+                    double x[N1], y[N1];
+#pragma unroll
+                    for (int k = 0; k < N1; ++k) x[k] = s[k * N1 * N1];
+#pragma unroll
+                    for (int c = 0; c < N1; ++c) {
+                        double t = 0.0;
+#pragma unroll
+                        for (int k = 0; k < N1; ++k) t += RL.proj[c][k] * x[k];
+                        y[c] = t;
+                    }
+#pragma unroll
+                    for (int c = 0; c < N1; ++c) s[c * N1 * N1] = y[c];
+                }
+                __syncthreads();
+            }
+            // derivative along d and time integral into the new modes
+#pragma unroll
+            for (int r = 0; r < S::TPL; ++r) {
+                const int t = lane + 64 * r;
+                if (t < S::NTGT) {
+                    const int z = t / (MT * NV), rem = t % (MT * NV), mt = rem / NV, v = rem % NV;
+                    const double* s = sr + z * SL + v * NS;
+                    double sum = 0.0;
+                    const int cnt = AT.n[d][mt];
+                    for (int q = 0; q < cnt; ++q)
+                        if (AT.ep[d][mt][q] < ne) sum += AT.coef[d][mt][q] * s[AT.off[d][mt][q]];
+                    acc[r] -= lam[d] * sum;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < S::TPL; ++r) {
+            const int t = lane + 64 * r;
+            if (t < S::NTGT) {
+                const int z = t / (MT * NV), rem = t % (MT * NV), mt = rem / NV, v = rem % NV;
+                sq[(z * MST + MS + mt) * NV + v] = acc[r];
+            }
+        }
+        __syncthreads();
+    }
+
+    if (Qout) {
+        for (int t = lane; t < ZPW * MST * NV; t += 64) {
+            const int z = t / (MST * NV), r = t % (MST * NV);
+            const long long zone = zbase + z;
+            if (zone < nR) Qout[(long long)r * nR + zone] = sq[t];
+        }
+    }
+    // face-point states: side 0 at xi_d = -1/2, side 1 at +1/2; point index
+    // (time, first tangential axis[, second tangential axis]) with time slowest.
+    // A zone with an inadmissible node or face state falls back to its mean.
+    constexpr double g = 0.28867513459481288225;
+    constexpr int FPL = (ZPW * S::NFPZ + 63) / 64;    // face points per lane
+    double Ufp[FPL][NV];
+#pragma unroll
+    for (int r = 0; r < FPL; ++r) {
+        const int t = lane + 64 * r;
+        if (t >= ZPW * S::NFPZ) continue;
+        const int z = t / S::NFPZ, rr = t % S::NFPZ;
+        const int d = rr / (2 * S::NPT), side = (rr / S::NPT) & 1, pt = rr % S::NPT;
+        const int t1 = (d == 0) ? 1 : 0;          // first tangential axis
+        int lt, a1, a2 = 0;
+        if (D == 3) { lt = pt >> 2; a1 = (pt >> 1) & 1; a2 = pt & 1; }
+        else { lt = pt >> 1; a1 = pt & 1; }
+        const double xn = side ? 0.5 : -0.5;
+        const double x1 = a1 ? g : -g, x2 = a2 ? g : -g;
+        // axis ax gets the normal coordinate, the first or the second tangential one
+        const double cx = (d == 0) ? xn : x1;
+        const double cy = (d == 1) ? xn : (t1 == 1 ? x1 : x2);
+        const double cz = (D == 3) ? ((d == 2) ? xn : x2) : 0.0;
+        const double tau = 0.5 + (lt ? g : -g);
+        double bx[P + 1], by[P + 1], bz[P + 1], bt[P + 1];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            bx[a] = mleg(a, cx);
+            by[a] = mleg(a, cy);
+            bz[a] = mleg(a, cz);
+        }
+        bt[0] = 1.0;
+#pragma unroll
+        for (int e = 1; e <= P; ++e) bt[e] = bt[e - 1] * tau;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Ufp[r][v] = 0.0;
+        const double* qz = sq + z * MST * NV;
+#pragma unroll
+        for (int m = 0; m < MST; ++m) {
+            const double phi = bx[M.a[m]] * by[M.b[m]] * bz[M.c[m]] * bt[M.e[m]];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Ufp[r][v] += qz[m * NV + v] * phi;
+        }
+        if (positivity && !admissible<D>(Ufp[r], gm1)) atomicOr(&sbad[z], 1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < FPL; ++r) {
+        const int t = lane + 64 * r;
+        if (t >= ZPW * S::NFPZ) continue;
+        const int z = t / S::NFPZ, rr = t % S::NFPZ;
+        const long long zone = zbase + z;
+        if (zone >= nR) continue;
+        const bool fb = sbad[z] != 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            FP[((long long)rr * NV + v) * nR + zone] = fb ? sq[z * MST * NV + v] : Ufp[r][v];
+    }
+    if (positivity && lane == 0) {
+        unsigned long long nb = 0;
+        for (int z = 0; z < ZPW; ++z) nb += (sbad[z] != 0 && zbase + z < nR) ? 1ull : 0ull;
+        if (nb) atomicAdd(&info->fallback, nb);
+    }
+}
+
+// ------------------------------------------------------------------------
+// a5: Riemann solver at the face Gauss points and the space-time average of
+// the face flux.  One thread per face along axis dir.
+// ------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_riemann(const double* __restrict__ FP, Box R, Box FB, int dir,
+                                                 int solver, double gamma, double* __restrict__ F)
+{
+    constexpr int NV = D + 2;
+    constexpr int NPT = 1 << D;
+    const long long nF = box_size(FB), nR = box_size(R);
+    const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nF) return;
+    int i, j, k;
+    box_ijk(FB, f, i, j, k);
+    const long long zl = box_index(R, i, j, k);
+    const long long zr = box_index(R, i + (dir == 0), j + (dir == 1), k + (dir == 2));
+    double Fb[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fb[v] = 0.0;
+    constexpr double w = 1.0 / NPT;
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+        double UL[NV], UR[NV], Fp[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            UL[v] = FP[((long long)((dir * 2 + 1) * NPT + pt) * NV + v) * nR + zl];
+            UR[v] = FP[((long long)((dir * 2 + 0) * NPT + pt) * NV + v) * nR + zr];
+        }
+        riemann<D>(UL, UR, dir, solver, gamma, Fp);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fb[v] += w * Fp[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v * nF + f] = Fb[v];
+}
+
+// ------------------------------------------------------------------------
+// a6 + a7: conservative update into the other state buffer (always FP64),
+// then the CFL signal speed of the new state.
+// ------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_update(const double* __restrict__ Uo, double* __restrict__ Un, Pad p,
+                                                Box I, const double* __restrict__ Fx, Box FBx,
+                                                const double* __restrict__ Fy, Box FBy,
+                                                const double* __restrict__ Fz, Box FBz, StepInfo* info,
+                                                double gamma, double ih0, double ih1, double ih2)
+{
+    constexpr int NV = D + 2;
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    bool ok = true;
+    if (z < box_size(I)) {
+        int i, j, k;
+        box_ijk(I, z, i, j, k);
+        const long long pi = pad_index(p, i, j, k);
+        const double lx = info->lam[0], ly = info->lam[1], lz = info->lam[2];
+        const long long nx = box_size(FBx), ny = box_size(FBy);
+        const long long xm = box_index(FBx, i - 1, j, k), xp = box_index(FBx, i, j, k);
+        const long long ym = box_index(FBy, i, j - 1, k), yp = box_index(FBy, i, j, k);
+        double u[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double q = Uo[v * p.vs + pi];
+            q = q - lx * (Fx[v * nx + xp] - Fx[v * nx + xm]);
+            q = q - ly * (Fy[v * ny + yp] - Fy[v * ny + ym]);
+            if constexpr (D == 3) {
+                const long long nz = box_size(FBz);
+                const long long zm = box_index(FBz, i, j, k - 1), zp = box_index(FBz, i, j, k);
+                q = q - lz * (Fz[v * nz + zp] - Fz[v * nz + zm]);
+            }
+            u[v] = q;
+            Un[v * p.vs + pi] = q;
+        }
+        s = signal_speed<D>(u, gamma, ih0, ih1, ih2, ok);
+    }
+    cfl_reduce<D>(s, ok, z, info);
+}
+
+// ------------------------------------------------------------------------
+// State transfer between a user buffer and the padded interior.
+// ------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_pack(const double* __restrict__ src, double* __restrict__ U, Pad p,
+                                              Box I, int aos)
+{
+    constexpr int NV = D + 2;
+    const long long N = box_size(I);
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= N) return;
+    int i, j, k;
+    box_ijk(I, z, i, j, k);
+    const long long pi = pad_index(p, i, j, k);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U[v * p.vs + pi] = aos ? src[z * NV + v] : src[v * N + z];
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_unpack(const double* __restrict__ U, double* __restrict__ dst, Pad p,
+                                                Box I, int aos)
+{
+    constexpr int NV = D + 2;
+    const long long N = box_size(I);
+    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (z >= N) return;
+    int i, j, k;
+    box_ijk(I, z, i, j, k);
+    const long long pi = pad_index(p, i, j, k);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double x = U[v * p.vs + pi];
+        if (aos) dst[z * NV + v] = x;
+        else dst[v * N + z] = x;
+    }
+}
+
+} // namespace hog

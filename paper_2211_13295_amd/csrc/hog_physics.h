@@ -1,0 +1,205 @@
+// hog_physics.h -- pointwise device routines of the ADER-WENO Euler update:
+// equation of state, physical fluxes, Riemann solvers and the 1D WENO
+// operator.  These are the "routine seq" pieces of the paper's structure
+// (Sec. II.1: Predictor_Ptwise, Riemann_Solver_Ptwise, Eval_Tstep_Ptwise),
+// written as inlined device functions on registers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hog {
+
+struct WenoArgs {
+    double eps;      // epsilon of the nonlinear weights
+    double g[4];     // O3: (L, C, R, -); O4: (H, L, C, R)
+    int linear;      // 1: weights fixed to the linear ones
+};
+
+// Pressure of an ideal gas from the conserved variables of D dimensions.
+template <int D>
+__device__ __forceinline__ double pressure(const double* U, double gm1)
+{
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) ke += U[1 + d] * U[1 + d];
+    return gm1 * (U[D + 1] - 0.5 * ke / U[0]);
+}
+
+// rho > 0, p > 0 and both finite.
+template <int D>
+__device__ __forceinline__ bool admissible(const double* U, double gm1)
+{
+    const double p = pressure<D>(U, gm1);
+    return U[0] > 0.0 && p > 0.0 && isfinite(U[0]) && isfinite(p);
+}
+
+// Physical fluxes of the Euler equations along all D axes at one point;
+// returns whether the state is admissible (rho > 0, p > 0, finite).
+template <int D>
+__device__ __forceinline__ bool fluxes(const double* U, double gm1, double (*F)[D + 2])
+{
+    const double rho = U[0];
+    const double ir = 1.0 / rho;
+    double u[D];
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) { u[d] = U[1 + d] * ir; ke += U[1 + d] * u[d]; }
+    const double p = gm1 * (U[D + 1] - 0.5 * ke);
+    const double Ep = U[D + 1] + p;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        F[d][0] = U[1 + d];
+#pragma unroll
+        for (int k = 0; k < D; ++k) F[d][1 + k] = U[1 + k] * u[d] + (k == d ? p : 0.0);
+        F[d][D + 1] = Ep * u[d];
+    }
+    return rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p);
+}
+
+// Flux of one axis.
+template <int D>
+__device__ __forceinline__ void flux_dir(const double* U, double gm1, int dir, double* F, double& p, double& un)
+{
+    const double ir = 1.0 / U[0];
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) ke += U[1 + d] * U[1 + d];
+    p = gm1 * (U[D + 1] - 0.5 * ke * ir);
+    un = U[1 + dir] * ir;
+    F[0] = U[1 + dir];
+#pragma unroll
+    for (int k = 0; k < D; ++k) F[1 + k] = U[1 + k] * un + (k == dir ? p : 0.0);
+    F[D + 1] = (U[D + 1] + p) * un;
+}
+
+// Riemann solvers at a face with normal axis dir.  solver: 0 HLLC, 1 HLL, 2 Rusanov.
+// HLLC follows Toro, Spruce and Speares with Einfeldt wave-speed bounds built
+// from Roe averages; branch ties resolved as S_L >= 0 -> left, S* >= 0 -> left
+// star, S_R > 0 -> right star, else right.
+template <int D>
+__device__ __forceinline__ void riemann(const double* UL, const double* UR, int dir, int solver,
+                                        double gamma, double* F)
+{
+    constexpr int NV = D + 2;
+    const double gm1 = gamma - 1.0;
+    double FL[NV], FR[NV], pL, pR, uL, uR;
+    flux_dir<D>(UL, gm1, dir, FL, pL, uL);
+    flux_dir<D>(UR, gm1, dir, FR, pR, uR);
+    const double rL = UL[0], rR = UR[0];
+    const double cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+    if (solver == 2) {
+        const double s = fmax(fabs(uL) + cL, fabs(uR) + cR);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * s * (UR[v] - UL[v]);
+        return;
+    }
+    const double sL = sqrt(rL), sR = sqrt(rR);
+    const double isum = 1.0 / (sL + sR);
+    const double HL = (UL[NV - 1] + pL) / rL, HR = (UR[NV - 1] + pR) / rR;
+    double q2 = 0.0, utn = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double ut = (UL[1 + d] / sL + UR[1 + d] / sR) * isum;
+        q2 += ut * ut;
+        if (d == dir) utn = ut;
+    }
+    const double Ht = (sL * HL + sR * HR) * isum;
+    const double ct = sqrt(gm1 * (Ht - 0.5 * q2));
+    const double SL = fmin(uL - cL, utn - ct);
+    const double SR = fmax(uR + cR, utn + ct);
+    if (solver == 1) {
+        if (SL >= 0.0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[v] = FL[v];
+        } else if (SR <= 0.0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[v] = FR[v];
+        } else {
+            const double id = 1.0 / (SR - SL);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) * id;
+        }
+        return;
+    }
+    const double mL = rL * (SL - uL), mR = rR * (SR - uR);
+    const double Ss = (pR - pL + mL * uL - mR * uR) / (mL - mR);
+    if (SL >= 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] = FL[v];
+        return;
+    }
+    if (SR <= 0.0 && !(Ss >= 0.0)) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) F[v] = FR[v];
+        return;
+    }
+    // star state on the side the contact leaves behind
+    const bool left = Ss >= 0.0;
+    const double* Uk = left ? UL : UR;
+    const double* Fk = left ? FL : FR;
+    const double Sk = left ? SL : SR;
+    const double rk = left ? rL : rR;
+    const double uk = left ? uL : uR;
+    const double pk = left ? pL : pR;
+    const double mk = left ? mL : mR;
+    const double f = mk / (Sk - Ss);
+    const double irk = 1.0 / rk;
+    double Us[NV];
+    Us[0] = f;
+#pragma unroll
+    for (int d = 0; d < D; ++d) Us[1 + d] = f * (d == dir ? Ss : Uk[1 + d] * irk);
+    Us[NV - 1] = f * (Uk[NV - 1] * irk + (Ss - uk) * (Ss + pk / mk));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = Fk[v] + Sk * (Us[v] - Uk[v]);
+}
+
+// 1D WENO operator on five zone averages v[0..4] (offsets -2..2): returns the
+// undivided Legendre coefficients c[1..P] of the zone polynomial.  P = 2:
+// convex combination of the three quadratics; P = 3: WENO-AO combination of
+// the cubic truncation of the centred quartic fit with the three quadratics.
+template <int P>
+__device__ __forceinline__ void weno1d(const double* v, double* c, const WenoArgs& wa)
+{
+    // quadratic candidates on {-2,-1,0}, {-1,0,1}, {0,1,2}
+    const double l1 = 0.5 * v[0] - 2.0 * v[1] + 1.5 * v[2];
+    const double l2 = 0.5 * v[0] - v[1] + 0.5 * v[2];
+    const double m1 = 0.5 * (v[3] - v[1]);
+    const double m2 = 0.5 * v[1] - v[2] + 0.5 * v[3];
+    const double r1 = -1.5 * v[2] + 2.0 * v[3] - 0.5 * v[4];
+    const double r2 = 0.5 * v[2] - v[3] + 0.5 * v[4];
+    constexpr double k13_3 = 13.0 / 3.0;
+    if constexpr (P == 2) {
+        double wL = wa.g[0], wC = wa.g[1], wR = wa.g[2];
+        if (!wa.linear) {
+            const double bL = wa.eps + (l1 * l1 + k13_3 * l2 * l2);
+            const double bC = wa.eps + (m1 * m1 + k13_3 * m2 * m2);
+            const double bR = wa.eps + (r1 * r1 + k13_3 * r2 * r2);
+            const double aL = wa.g[0] / (bL * bL), aC = wa.g[1] / (bC * bC), aR = wa.g[2] / (bR * bR);
+            const double is = 1.0 / (aL + aC + aR);
+            wL = aL * is; wC = aC * is; wR = aR * is;
+        }
+        c[1] = wL * l1 + wC * m1 + wR * r1;
+        c[2] = wL * l2 + wC * m2 + wR * r2;
+    } else {
+        const double h1 = (11.0 * (v[0] - v[4]) + 82.0 * (v[3] - v[1])) * (1.0 / 120.0);
+        const double h2 = (-3.0 * (v[0] + v[4]) + 40.0 * (v[1] + v[3]) - 74.0 * v[2]) * (1.0 / 56.0);
+        const double h3 = ((v[4] - v[0]) + 2.0 * (v[1] - v[3])) * (1.0 / 12.0);
+        const double gH = wa.g[0], gL = wa.g[1], gC = wa.g[2], gR = wa.g[3];
+        double wH = gH, wL = gL, wC = gC, wR = gR;
+        if (!wa.linear) {
+            const double s1 = h1 + 0.1 * h3;
+            const double bH = wa.eps + (s1 * s1 + k13_3 * h2 * h2 + (781.0 / 20.0) * h3 * h3);
+            const double bL = wa.eps + (l1 * l1 + k13_3 * l2 * l2);
+            const double bC = wa.eps + (m1 * m1 + k13_3 * m2 * m2);
+            const double bR = wa.eps + (r1 * r1 + k13_3 * r2 * r2);
+            const double aH = gH / (bH * bH), aL = gL / (bL * bL), aC = gC / (bC * bC), aR = gR / (bR * bR);
+            const double is = 1.0 / (aH + aL + aC + aR);
+            wH = aH * is; wL = aL * is; wC = aC * is; wR = aR * is;
+        }
+        const double r = wH / gH;
+        c[1] = r * (h1 - gL * l1 - gC * m1 - gR * r1) + wL * l1 + wC * m1 + wR * r1;
+        c[2] = r * (h2 - gL * l2 - gC * m2 - gR * r2) + wL * l2 + wC * m2 + wR * r2;
+        c[3] = r * h3;
+    }
+}
+
+} // namespace hog

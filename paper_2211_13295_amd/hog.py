@@ -1,0 +1,232 @@
+"""Thin ctypes binding of the C ABI in include/hog.h (argument marshalling only).
+
+Every step of the update runs in the gfx950 kernels of ``libhog.so``; this
+module only fills the config struct, allocates the caller-side workspace with
+PyTorch (device memory) and passes pointers and the current HIP stream.  If
+the library is missing or cannot be loaded it raises: there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhog.so")
+
+HOG_OK, HOG_EINVAL, HOG_ENOMEM, HOG_EDEVICE, HOG_ENONPHYS, HOG_ESTATE = 0, -1, -2, -3, -4, -5
+SOA, AOS = 0, 1
+HOST, DEVICE = 0, 1
+TAP_MODES, TAP_STMODES, TAP_FLUX_X, TAP_FLUX_Y, TAP_FLUX_Z = 1, 2, 3, 4, 5
+RIEMANN = {"hllc": 0, "hll": 1, "rusanov": 2}
+BC = {"periodic": 0, "outflow": 1}
+_ERRNAMES = {HOG_EINVAL: "EINVAL", HOG_ENOMEM: "ENOMEM", HOG_EDEVICE: "EDEVICE",
+             HOG_ENONPHYS: "ENONPHYS", HOG_ESTATE: "ESTATE"}
+
+
+class HogError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hog error {_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class HogConfig(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("order", C.c_int), ("riemann", C.c_int), ("bc", C.c_int * 3),
+        ("precision", C.c_int), ("linear_weno", C.c_int), ("debug", C.c_int),
+        ("positivity", C.c_int), ("reserved", C.c_int * 3),
+        ("gamma", C.c_double), ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+        ("cfl", C.c_double), ("weno_eps", C.c_double), ("g3", C.c_double * 3), ("g4", C.c_double * 4),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libhog.so (built by paper_2211_13295_amd/build.py); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not found: build it with `python paper_2211_13295_amd/build.py`")
+    L = C.CDLL(LIB_PATH)
+    vp, cp = C.c_void_p, C.POINTER(HogConfig)
+    L.hog_abi_version.restype = C.c_int
+    L.hog_last_error.restype = C.c_char_p
+    L.hog_workspace_size.argtypes = [cp, C.POINTER(C.c_size_t)]
+    L.hog_create.argtypes = [cp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.hog_destroy.argtypes = [vp]
+    L.hog_set_state.argtypes = [vp, vp, C.c_int, C.c_int]
+    L.hog_get_state.argtypes = [vp, vp, C.c_int, C.c_int]
+    L.hog_compute_dt.argtypes = [vp, C.POINTER(C.c_double)]
+    L.hog_step.argtypes = [vp, C.c_double, vp]
+    L.hog_advance.argtypes = [vp, C.c_int, C.c_double, C.POINTER(C.c_double)]
+    L.hog_debug_tap.argtypes = [vp, C.c_int, vp, C.c_size_t]
+    L.hog_profile_enable.argtypes = [vp, C.c_int]
+    L.hog_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_int]
+    L.hog_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
+    L.hog_last_bad_zone.argtypes = [vp]
+    L.hog_last_bad_zone.restype = C.c_longlong
+    for f in ("hog_workspace_size", "hog_create", "hog_destroy", "hog_set_state", "hog_get_state",
+              "hog_compute_dt", "hog_step", "hog_advance", "hog_debug_tap", "hog_profile_enable",
+              "hog_profile_read", "hog_stats"):
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != HOG_OK:
+        raise HogError(rc, load().hog_last_error().decode())
+
+
+def make_config(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("periodic",) * 3,
+                linear_weno=False, debug=False, weno_eps=0.0, g3=(0, 0, 0), g4=(0, 0, 0, 0),
+                positivity=True):
+    c = HogConfig()
+    c.ndim = ndim
+    c.nx, c.ny = int(n[0]), int(n[1])
+    c.nz = int(n[2]) if ndim == 3 else 1
+    c.order = order
+    c.riemann = RIEMANN[riemann] if isinstance(riemann, str) else int(riemann)
+    for d in range(3):
+        c.bc[d] = BC[bc[d]] if isinstance(bc[d], str) else int(bc[d])
+    c.precision = 0
+    c.linear_weno = int(bool(linear_weno))
+    c.debug = int(bool(debug))
+    c.positivity = int(bool(positivity))
+    c.gamma = gamma
+    c.dx, c.dy = h[0], h[1]
+    c.dz = h[2] if ndim == 3 else 1.0
+    c.cfl = cfl
+    c.weno_eps = weno_eps
+    for i in range(3):
+        c.g3[i] = g3[i]
+    for i in range(4):
+        c.g4[i] = g4[i]
+    return c
+
+
+def workspace_size(cfg):
+    n = C.c_size_t(0)
+    _check(load().hog_workspace_size(C.byref(cfg), C.byref(n)))
+    return n.value
+
+
+class Grid:
+    """One ADER-WENO grid on the current GPU and the current torch stream."""
+
+    def __init__(self, ndim, n, order, h, **kw):
+        import torch
+        self._torch = torch
+        self.cfg = make_config(ndim, n, order, h, **kw)
+        self.ndim, self.order = ndim, order
+        self.nv = ndim + 2
+        self.n = (self.cfg.nx, self.cfg.ny, self.cfg.nz)
+        self.shape = (self.nv, self.n[2], self.n[1], self.n[0]) if ndim == 3 else (self.nv, self.n[1], self.n[0])
+        self.nzones = self.n[0] * self.n[1] * self.n[2]
+        L = load()
+        nbytes = workspace_size(self.cfg)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream()
+        h_ = C.c_void_p()
+        _check(L.hog_create(C.byref(self.cfg), C.c_void_p(aligned), nbytes,
+                            C.c_void_p(self.stream.cuda_stream), C.byref(h_)))
+        self._h = h_
+
+    @classmethod
+    def from_problem(cls, pb, order, **kw):
+        kw.setdefault("gamma", pb.gamma)
+        kw.setdefault("bc", pb.bc)
+        g = cls(pb.ndim, pb.n, order, pb.h, **kw)
+        g.set_state(pb.U)
+        return g
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hog_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, U, layout=SOA):
+        torch = self._torch
+        if isinstance(U, torch.Tensor) and U.is_cuda:
+            t = U.contiguous().to(torch.float64)
+            assert t.numel() == self.nv * self.nzones
+            _check(load().hog_set_state(self._h, C.c_void_p(t.data_ptr()), layout, DEVICE))
+            torch.cuda.current_stream().synchronize()
+            return
+        a = np.ascontiguousarray(U, dtype=np.float64)
+        assert a.size == self.nv * self.nzones
+        _check(load().hog_set_state(self._h, a.ctypes.data_as(C.c_void_p), layout, HOST))
+
+    def get_state(self, layout=SOA):
+        shape = self.shape if layout == SOA else self.shape[1:] + (self.nv,)
+        out = np.empty(shape, dtype=np.float64)
+        _check(load().hog_get_state(self._h, out.ctypes.data_as(C.c_void_p), layout, HOST))
+        return out
+
+    def get_state_device(self, out, layout=SOA):
+        _check(load().hog_get_state(self._h, C.c_void_p(out.data_ptr()), layout, DEVICE))
+        return out
+
+    def compute_dt(self):
+        dt = C.c_double(0.0)
+        _check(load().hog_compute_dt(self._h, C.byref(dt)))
+        return dt.value
+
+    def step(self, dt, want_next=True):
+        nxt = C.c_double(0.0)
+        _check(load().hog_step(self._h, float(dt), C.byref(nxt) if want_next else None))
+        return nxt.value if want_next else None
+
+    def advance(self, nsteps, t_end=0.0):
+        t = C.c_double(0.0)
+        _check(load().hog_advance(self._h, int(nsteps), float(t_end), C.byref(t)))
+        return t.value
+
+    def tap(self, which):
+        nd, nv, p = self.ndim, self.nv, self.order - 1
+        from math import comb
+        if which == TAP_MODES:
+            shape = (self.nzones, comb(p + nd, nd), nv)
+        elif which == TAP_STMODES:
+            shape = (self.nzones, comb(p + nd + 1, nd + 1), nv)
+        else:
+            d = which - TAP_FLUX_X
+            n = list(self.n)
+            n[d] += 1
+            shape = (nv, n[2], n[1], n[0])
+        out = np.empty(shape, dtype=np.float64)
+        _check(load().hog_debug_tap(self._h, which, out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    STAGES = ("ghost", "reconstruction", "predictor", "riemann", "update")
+
+    def profile(self, enable=True):
+        _check(load().hog_profile_enable(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        n = len(self.STAGES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int * n)()
+        _check(load().hog_profile_read(self._h, ms, cnt, n))
+        return {s: (ms[i], cnt[i]) for i, s in enumerate(self.STAGES)}
+
+    def stats(self):
+        t, dt, nb = C.c_double(0), C.c_double(0), C.c_longlong(0)
+        _check(load().hog_stats(self._h, C.byref(t), C.byref(dt), C.byref(nb)))
+        return {"t": t.value, "dt": dt.value, "fallback_zones": nb.value}
+
+    def last_bad_zone(self):
+        return load().hog_last_bad_zone(self._h)

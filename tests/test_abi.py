@@ -1,0 +1,58 @@
+"""The C-ABI library loads and exports every function include/hog.h declares
+(no compute call: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2211_13295_amd", "libhog.so")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hog.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(hog_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("hog_create", "hog_destroy", "hog_set_state", "hog_get_state", "hog_compute_dt",
+                     "hog_step", "hog_advance", "hog_workspace_size", "hog_last_error"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhog.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    lib.hog_abi_version.restype = ctypes.c_int
+    assert lib.hog_abi_version() == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhog.so not built")
+def test_invalid_configs_are_rejected_without_a_device():
+    from paper_2211_13295_amd import hog
+    c = hog.make_config(3, (8, 8, 8), 4, (0.1, 0.1, 0.1))
+    assert hog.workspace_size(c) > 0
+    for field, val in (("ndim", 4), ("order", 5), ("nx", 0), ("cfl", 1.5), ("gamma", 1.0), ("riemann", 7)):
+        bad = hog.make_config(3, (8, 8, 8), 4, (0.1, 0.1, 0.1))
+        setattr(bad, field, val)
+        with pytest.raises(hog.HogError) as e:
+            hog.workspace_size(bad)
+        assert e.value.code == hog.HOG_EINVAL
+    bad = hog.make_config(3, (2, 8, 8), 4, (0.1, 0.1, 0.1))   # periodic axis too short
+    with pytest.raises(hog.HogError):
+        hog.workspace_size(bad)
+
+
+def test_product_package_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2211_13295_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt and "liboracle" not in txt, f

@@ -133,3 +133,37 @@ def test_entropy_wave_3d_order():
         ex = icgen.entropy_wave(n=n, ndim=3, amp=0.1, vel=(1.0, 0.5, 0.25), t=t).U
         errs.append(np.abs(U[0] - ex[0]).mean())
     assert np.log2(errs[0] / errs[1]) > 2.6, errs
+
+
+def test_positivity_fallback_carries_the_blast_and_stays_conservative():
+    """Fourth order on conserved variables is not positivity preserving at a
+    100:1 pressure jump: without the first-order zone fallback the first step
+    already fails; with it the run stays admissible and conservative."""
+    pb24 = icgen.multiblast(n=24, seed=3)
+    off = oracle.cfg_from_problem(pb24, 4, positivity=False)
+    dt, _ = oracle.cfl_dt(off, pb24.U)
+    U1 = oracle.step(off, pb24.U, dt)
+    assert oracle.cfl_dt(off, U1)[0] < 0
+    pb = icgen.multiblast(n=16, seed=3)
+    # periodic box so that conservation is exact (spheres may cross the boundary)
+    on = oracle.make_cfg(3, pb.n, 4, pb.h, bc=("periodic",) * 3)
+    U = pb.U
+    hits = 0
+    for _ in range(4):
+        dt, bad = oracle.cfl_dt(on, U)
+        assert bad < 0
+        U, nb = oracle.step_count(on, U, dt)
+        hits += nb
+    assert hits > 0
+    assert oracle.cfl_dt(on, U)[1] < 0
+    tot0, tot1 = pb.U.sum(axis=(1, 2, 3)), U.sum(axis=(1, 2, 3))
+    scale = np.maximum(np.abs(pb.U).sum(axis=(1, 2, 3)), np.abs(U).sum(axis=(1, 2, 3)))
+    assert (np.abs(tot1 - tot0) / scale).max() < 1e-13
+
+
+def test_fallback_never_triggers_on_smooth_data():
+    pb = icgen.vortex3d_perturbed(n=12, seed=2)
+    c = oracle.cfg_from_problem(pb, 4)
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    _, nb = oracle.step_count(c, pb.U, dt)
+    assert nb == 0
