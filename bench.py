@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain elementwise copy of 2 x 1 GiB (known bytes) to "
+                         "calibrate the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU path (halo exchange and a min "
@@ -152,6 +155,14 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     hog.load()
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)            # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        print(f"copy calibration: 3 launches of {x.numel() * 8} bytes read + written", flush=True)
+        del x, y
     n, order = args.n, args.order
     pb = icgen.vortex3d_perturbed(n=n, seed=2)
     g = hog.Grid.from_problem(pb, order)

@@ -265,7 +265,7 @@ def test_error_paths(hog):
     assert e.value.code == hog.HOG_ENONPHYS
     assert g.last_bad_zone() == (1 * 6 + 2) * 6 + 3
     # a step that blows up keeps the pre-step state
-    sm = icgen.random_smooth(n=(8, 8, 8), ndim=3, seed=2, amp=0.3)
+    sm = icgen.random_smooth(n=(6, 6, 6), ndim=3, seed=2, amp=0.3)
     g.set_state(sm.U)
     with pytest.raises(hog.HogError) as e:
         g.step(50.0)
