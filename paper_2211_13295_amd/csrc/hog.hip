@@ -222,8 +222,9 @@ int enqueue_step_t(hog_grid* g, double dt_user)
     {
         StageMark m(g, 2);
         using S = PredShape<D, P>;
-        k_predict<D, P><<<nblocks(box_size(L.R), S::ZPW), 64, 0, s>>>(g->W, L.R, g->info, g->cfg.gamma,
-                                                                       g->cfg.positivity, g->FP, g->Q);
+        const long long ngroups = (box_size(L.R) + S::ZPW - 1) / S::ZPW;
+        k_predict<D, P><<<xcd_blocks(ngroups), 64, 0, s>>>(g->W, L.R, g->info, g->cfg.gamma, g->cfg.positivity,
+                                                            g->FP, g->Q);
     }
     {
         StageMark m(g, 3);

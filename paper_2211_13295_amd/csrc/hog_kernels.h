@@ -264,14 +264,19 @@ __global__ __launch_bounds__(256) void k_recon_z(const double* __restrict__ B, B
 }
 
 // ------------------------------------------------------------------------
-// a4: ADER predictor.  One wavefront per zone group: lane = (zone slot,
-// spatial Gauss node).  Per Picard iteration each lane evaluates q at its
-// node for every time node, forms the physical fluxes and contracts them
-// against the time basis; the spatial L2 projection is then done as a
-// sum-factorised x -> y -> z transform in LDS, one flux direction at a time,
-// and the derivative / time-integral maps add the result into the new
-// space-time modes.  After the last iteration the face-point states needed
-// by the Riemann solver are evaluated from the final modes.
+// a4: ADER predictor.  One wavefront per zone group.  Node phase: lane =
+// (zone slot, spatial Gauss node); each lane keeps the time-independent part
+// of q at its node in registers, evaluates the time modes from LDS, forms the
+// physical fluxes at every time node and contracts them against the time
+// basis.  Projection phase: the contracted fluxes go to LDS as one row per
+// (zone, flux time mode, axis, variable) "slice"; one lane then owns a whole
+// slice and does its x -> y -> z sum-factorised L2 projection in registers,
+// writing the modal coefficients back over its own row.  Assembly phase:
+// lanes own new-mode targets and add the derivative / time-integral terms.
+// After the last iteration the face-point states for the Riemann solver are
+// evaluated from the final modes.  Blocks are mapped to zone groups so that
+// the blocks one XCD runs (every 8th block) take contiguous zones and share
+// their L2 cache lines.
 // ------------------------------------------------------------------------
 template <int D, int P>
 struct PredShape {
@@ -283,83 +288,127 @@ struct PredShape {
     static constexpr int MST = Modes<D, P>::NST;
     static constexpr int MT = MST - MS;              // modes with e >= 1
     static constexpr int NE = P;                     // flux time modes feeding a derivative
-    static constexpr int SL = NE * NV * NS;          // LDS slice doubles per zone
+    static constexpr int NSLZ = NE * D * NV;         // slices per zone
+    static constexpr int RS = NS + 2;                // slice row stride (doubles), padded against bank conflicts
     static constexpr int NPT = 1 << D;               // Gauss points per face (tangential x time)
     static constexpr int NFPZ = D * 2 * NPT;         // face points per zone
     static constexpr int NTGT = ZPW * MT * NV;       // new-mode targets per wavefront
     static constexpr int TPL = (NTGT + 63) / 64;     // targets per lane
-    static constexpr int MAXE = P * P;               // max source terms per target and axis
 };
 
-// For each axis d and target mode (e >= 1) the list of source flux modes:
-//  q[a..d..,e] -= lam_d * sum_{a'' > a_d, e'} D[a''][a_d] * I[e'][e] * f_d[.., a'' .., e']
+constexpr int kXcds = 8;   // MI355X: workgroups are dispatched round-robin over 8 XCDs
+
+// Block -> group index such that the blocks of one XCD cover a contiguous range.
+__device__ __forceinline__ int xcd_group(int b, int ngroups)
+{
+    const int per = (ngroups + kXcds - 1) / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+inline unsigned xcd_blocks(long long ngroups)
+{
+    const long long per = (ngroups + kXcds - 1) / kXcds;
+    return (unsigned)(per * kXcds);
+}
+
+// One target of the new space-time modes held by a lane.
+struct Target {
+    int valid, z, v, a, b, c, e;
+};
+
+// In-register L2 projection of one slice: node values row[n] (node index
+// (k*N1 + j)*N1 + i) -> modal coefficients written back to
+// row[(c*N1 + b)*N1 + a] for a + b + c <= P.  The node planes are streamed
+// (k outermost) into the modal accumulators, so only one plane is live.
 template <int D, int P>
-struct AsmTable {
-    using S = PredShape<D, P>;
-    int n[D][S::MT];
-    int off[D][S::MT][S::MAXE];     // LDS offset of the source, variable 0
-    int ep[D][S::MT][S::MAXE];      // its flux time mode e'
-    double coef[D][S::MT][S::MAXE];
-    constexpr AsmTable() : n{}, off{}, ep{}, coef{}
-    {
-        constexpr Modes<D, P> M{};
-        constexpr Rules<P> R{};
-        for (int d = 0; d < D; ++d)
-            for (int t = 0; t < S::MT; ++t) {
-                const int m = S::MS + t;
-                int tgt[3] = {M.a[m], M.b[m], M.c[m]};
-                const int e = M.e[m];
-                int cnt = 0;
-                for (int hi = tgt[d] + 1; hi <= P; ++hi)
-                    for (int epr = (e >= 1 ? e - 1 : 0); epr < S::NE; ++epr) {
-                        int src[3] = {tgt[0], tgt[1], tgt[2]};
-                        src[d] = hi;
-                        if (src[0] + src[1] + src[2] + epr > P) continue;
-                        const double cf = R.D[hi][tgt[d]] * R.I[epr][e];
-                        if (cf == 0.0) continue;
-                        const int spatial = (D == 3) ? (src[2] * S::N1 + src[1]) * S::N1 + src[0]
-                                                     : src[1] * S::N1 + src[0];
-                        off[d][t][cnt] = epr * S::NV * S::NS + spatial;
-                        ep[d][t][cnt] = epr;
-                        coef[d][t][cnt] = cf;
-                        ++cnt;
-                    }
-                n[d][t] = cnt;
+__device__ __forceinline__ void project_slice(double* row)
+{
+    constexpr int N1 = P + 1;
+    constexpr Rules<P> RL{};
+    if constexpr (D == 3) {
+        double out[N1][N1][N1] = {};   // [c][b][a], a + b + c <= P used
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+            double x[N1][N1];
+#pragma unroll
+            for (int j = 0; j < N1; ++j)
+#pragma unroll
+                for (int i = 0; i < N1; ++i) x[j][i] = row[(k * N1 + j) * N1 + i];
+            double t1[N1][N1];   // [j][a]
+#pragma unroll
+            for (int j = 0; j < N1; ++j)
+#pragma unroll
+                for (int a = 0; a <= P; ++a) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < N1; ++i) s += RL.proj[a][i] * x[j][i];
+                    t1[j][a] = s;
+                }
+#pragma unroll
+            for (int a = 0; a <= P; ++a)
+#pragma unroll
+                for (int b = 0; a + b <= P; ++b) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) s += RL.proj[b][j] * t1[j][a];
+#pragma unroll
+                    for (int c = 0; a + b + c <= P; ++c) out[c][b][a] += RL.proj[c][k] * s;
+                }
+        }
+#pragma unroll
+        for (int a = 0; a <= P; ++a)
+#pragma unroll
+            for (int b = 0; a + b <= P; ++b)
+#pragma unroll
+                for (int c = 0; a + b + c <= P; ++c) row[(c * N1 + b) * N1 + a] = out[c][b][a];
+    } else {
+        double x[N1][N1];
+#pragma unroll
+        for (int j = 0; j < N1; ++j)
+#pragma unroll
+            for (int i = 0; i < N1; ++i) x[j][i] = row[j * N1 + i];
+        double t1[N1][N1];       // [j][a]
+#pragma unroll
+        for (int j = 0; j < N1; ++j)
+#pragma unroll
+            for (int a = 0; a <= P; ++a) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < N1; ++i) s += RL.proj[a][i] * x[j][i];
+                t1[j][a] = s;
+            }
+#pragma unroll
+        for (int a = 0; a <= P; ++a)
+#pragma unroll
+            for (int b = 0; a + b <= P; ++b) {
+                double s = 0.0;
+#pragma unroll
+                for (int j = 0; j < N1; ++j) s += RL.proj[b][j] * t1[j][a];
+                row[b * N1 + a] = s;
             }
     }
-};
-
-__constant__ AsmTable<2, 2> c_asm22 = AsmTable<2, 2>();
-__constant__ AsmTable<2, 3> c_asm23 = AsmTable<2, 3>();
-__constant__ AsmTable<3, 2> c_asm32 = AsmTable<3, 2>();
-__constant__ AsmTable<3, 3> c_asm33 = AsmTable<3, 3>();
+}
 
 template <int D, int P>
-__device__ __forceinline__ const AsmTable<D, P>& asm_table();
-template <> __device__ __forceinline__ const AsmTable<2, 2>& asm_table<2, 2>() { return c_asm22; }
-template <> __device__ __forceinline__ const AsmTable<2, 3>& asm_table<2, 3>() { return c_asm23; }
-template <> __device__ __forceinline__ const AsmTable<3, 2>& asm_table<3, 2>() { return c_asm32; }
-template <> __device__ __forceinline__ const AsmTable<3, 3>& asm_table<3, 3>() { return c_asm33; }
-
-template <int D, int P>
-__global__ __launch_bounds__(64) void k_predict(const double* __restrict__ W, Box R,
+__global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W, Box R,
                                                 StepInfo* __restrict__ info, double gamma, int positivity,
                                                 double* __restrict__ FP, double* __restrict__ Qout)
 {
     using S = PredShape<D, P>;
-    constexpr int NV = S::NV, N1 = S::N1, NS = S::NS, ZPW = S::ZPW;
-    constexpr int MS = S::MS, MST = S::MST, MT = S::MT, NE = S::NE, SL = S::SL;
+    constexpr int NV = S::NV, N1 = S::N1, NS = S::NS, ZPW = S::ZPW, RS = S::RS;
+    constexpr int MS = S::MS, MST = S::MST, MT = S::MT, NE = S::NE, NSLZ = S::NSLZ;
     constexpr Modes<D, P> M{};
     constexpr Rules<P> RL{};
-    const AsmTable<D, P>& AT = asm_table<D, P>();
 
     __shared__ double sq[ZPW * MST * NV];
-    __shared__ double sr[ZPW * SL];
+    __shared__ double sr[ZPW * NSLZ * RS];
     __shared__ int sbad[ZPW];
 
     const long long nR = box_size(R);
+    const int ngroups = (int)((nR + ZPW - 1) / ZPW);
+    const int grp = xcd_group(blockIdx.x, ngroups);
+    if (grp >= ngroups) return;                       // whole wavefront, before any barrier
     const int lane = threadIdx.x;
-    const long long zbase = (long long)blockIdx.x * ZPW;
+    const long long zbase = (long long)grp * ZPW;
     const double gm1 = gamma - 1.0;
     const double lam[3] = {info->lam[0], info->lam[1], info->lam[2]};
 
@@ -384,181 +433,152 @@ __global__ __launch_bounds__(64) void k_predict(const double* __restrict__ W, Bo
             pz[a] = (D == 3) ? mleg(a, zn) : (a == 0 ? 1.0 : 0.0);
         }
     }
+    // the new-mode targets this lane accumulates
+    Target tg[S::TPL];
+#pragma unroll
+    for (int r = 0; r < S::TPL; ++r) {
+        const int t = lane + 64 * r;
+        tg[r].valid = t < S::NTGT;
+        const int tt = tg[r].valid ? t : 0;
+        tg[r].z = tt / (MT * NV);
+        const int rem = tt % (MT * NV), mt = rem / NV;
+        tg[r].v = rem % NV;
+        tg[r].a = tg[r].b = tg[r].c = tg[r].e = 0;
+#pragma unroll
+        for (int q = 0; q < MT; ++q)
+            if (q == mt) {
+                tg[r].a = M.a[MS + q];
+                tg[r].b = M.b[MS + q];
+                tg[r].c = M.c[MS + q];
+                tg[r].e = M.e[MS + q];
+            }
+    }
     __syncthreads();
 
-    for (int it = 0; it < P; ++it) {
-        const int ne = (it == 0) ? 1 : NE;   // first iterate is time-independent
-        double R[D][NE][NV];
+    // time-independent part of q at this lane's node (the reconstruction)
+    double Q0[NV];
 #pragma unroll
-        for (int d = 0; d < D; ++d)
+    for (int v = 0; v < NV; ++v) Q0[v] = 0.0;
+    if (active) {
+        const double* qz = sq + zs * MST * NV;
 #pragma unroll
-            for (int e = 0; e < NE; ++e)
+        for (int m = 0; m < MS; ++m) {
+            const double phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) R[d][e][v] = 0.0;
+            for (int v = 0; v < NV; ++v) Q0[v] += qz[m * NV + v] * phi;
+        }
+    }
 
+    for (int it = 0; it < P; ++it) {
+        const bool first = it == 0;            // first iterate is time-independent
+        const int ne = first ? 1 : NE;
+        // ---- node phase
         if (active) {
-            double Qe[P + 1][NV];
-#pragma unroll
-            for (int e = 0; e <= P; ++e)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Qe[e][v] = 0.0;
-            const double* qz = sq + zs * MST * NV;
-#pragma unroll
-            for (int m = 0; m < MST; ++m) {
-                if (it == 0 && M.e[m] != 0) continue;
-                const double phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Qe[M.e[m]][v] += qz[m * NV + v] * phi;
-            }
             bool ok = true;
-            if (it == 0) {
+            double* rz = sr + zs * NSLZ * RS + node;     // slice (e, d, v) at rz[((e*D + d)*NV + v)*RS]
+            if (first) {
                 double F[D][NV];
-                ok = fluxes<D>(Qe[0], gm1, F);
+                ok = fluxes<D>(Q0, gm1, F);
 #pragma unroll
                 for (int d = 0; d < D; ++d)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) R[d][0][v] = F[d][v];
+                    for (int v = 0; v < NV; ++v) rz[(d * NV + v) * RS] = F[d][v];
             } else {
+                double Qe[P][NV];                        // time modes e = 1..P at the node
+#pragma unroll
+                for (int e = 0; e < P; ++e)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Qe[e][v] = 0.0;
+                const double* qz = sq + zs * MST * NV;
+#pragma unroll
+                for (int m = MS; m < MST; ++m) {
+                    const double phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Qe[M.e[m] - 1][v] += qz[m * NV + v] * phi;
+                }
+                double Racc[NE][D][NV];
+#pragma unroll
+                for (int e = 0; e < NE; ++e)
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) Racc[e][d][v] = 0.0;
 #pragma unroll
                 for (int l = 0; l < N1; ++l) {
                     double U[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        double s = Qe[P][v];
+                        double s = Qe[P - 1][v];
 #pragma unroll
-                        for (int e = P - 1; e >= 0; --e) s = s * RL.t[l] + Qe[e][v];
-                        U[v] = s;
+                        for (int e = P - 2; e >= 0; --e) s = s * RL.t[l] + Qe[e][v];
+                        U[v] = Q0[v] + s * RL.t[l];
                     }
                     double F[D][NV];
                     ok = fluxes<D>(U, gm1, F) && ok;
 #pragma unroll
+                    for (int e = 0; e < NE; ++e)
+#pragma unroll
+                        for (int d = 0; d < D; ++d)
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) Racc[e][d][v] += RL.tproj[e][l] * F[d][v];
+                }
+#pragma unroll
+                for (int e = 0; e < NE; ++e)
+#pragma unroll
                     for (int d = 0; d < D; ++d)
 #pragma unroll
-                        for (int e = 0; e < NE; ++e)
-#pragma unroll
-                            for (int v = 0; v < NV; ++v) R[d][e][v] += RL.tproj[e][l] * F[d][v];
-                }
+                        for (int v = 0; v < NV; ++v) rz[((e * D + d) * NV + v) * RS] = Racc[e][d][v];
             }
             if (positivity && !ok) atomicOr(&sbad[zs], 1);
         }
-
-        double acc[S::TPL];
-#pragma unroll
-        for (int r = 0; r < S::TPL; ++r) acc[r] = 0.0;
-
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            __syncthreads();
-            if (active) {
-#pragma unroll
-                for (int e = 0; e < NE; ++e)
-                    if (e < ne) {
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) sr[zs * SL + (e * NV + v) * NS + node] = R[d][e][v];
-                    }
-            }
-            __syncthreads();
-            // x: contract node index i -> a'
-            {
-                const int nl = ZPW * ne * NV * (NS / N1);
-                for (int l = lane; l < nl; l += 64) {
-                    const int z = l / (ne * NV * (NS / N1));
-                    const int rem = l % (ne * NV * (NS / N1));
-                    const int ev = rem / (NS / N1), row = rem % (NS / N1);
-                    double* s = sr + z * SL + ev * NS + row * N1;
-                    double x[N1], y[N1];
-#pragma unroll
-                    for (int i = 0; i < N1; ++i) x[i] = s[i];
-#pragma unroll
-                    for (int a = 0; a < N1; ++a) {
-                        double t = 0.0;
-#pragma unroll
-                        for (int i = 0; i < N1; ++i) t += RL.proj[a][i] * x[i];
-                        y[a] = t;
-                    }
-#pragma unroll
-                    for (int a = 0; a < N1; ++a) s[a] = y[a];
-                }
-            }
-            __syncthreads();
-            // y: contract node index j -> b' (lines with a' <= P - e')
-            {
-                constexpr int NK = (D == 3) ? N1 : 1;
-                const int nl = ZPW * ne * NV * NK * N1;
-                for (int l = lane; l < nl; l += 64) {
-                    const int z = l / (ne * NV * NK * N1);
-                    int rem = l % (ne * NV * NK * N1);
-                    const int ev = rem / (NK * N1);
-                    rem %= (NK * N1);
-                    const int k = rem / N1, a = rem % N1;
-                    const int e = ev / NV;
-                    if (a > P - e) continue;
-                    double* s = sr + z * SL + ev * NS + k * N1 * N1 + a;
-                    double x[N1], y[N1];
-#pragma unroll
-                    for (int j = 0; j < N1; ++j) x[j] = s[j * N1];
-#pragma unroll
-                    for (int b = 0; b < N1; ++b) {
-                        double t = 0.0;
-#pragma unroll
-                        for (int j = 0; j < N1; ++j) t += RL.proj[b][j] * x[j];
-                        y[b] = t;
-                    }
-#pragma unroll
-                    for (int b = 0; b < N1; ++b) s[b * N1] = y[b];
-                }
-            }
-            __syncthreads();
-            if constexpr (D == 3) {
-                // z: contract node index k -> c' (lines with a' + b' <= P - e')
-                const int nl = ZPW * ne * NV * N1 * N1;
-                for (int l = lane; l < nl; l += 64) {
-                    const int z = l / (ne * NV * N1 * N1);
-                    int rem = l % (ne * NV * N1 * N1);
-                    const int ev = rem / (N1 * N1);
-                    rem %= (N1 * N1);
-                    const int b = rem / N1, a = rem % N1;
-                    const int e = ev / NV;
-                    if (a + b > P - e) continue;
-                    double* s = sr + z * SL + ev * NS + b * N1 + a;
-                    double x[N1], y[N1];
-#pragma unroll
-                    for (int k = 0; k < N1; ++k) x[k] = s[k * N1 * N1];
-#pragma unroll
-                    for (int c = 0; c < N1; ++c) {
-                        double t = 0.0;
-#pragma unroll
-                        for (int k = 0; k < N1; ++k) t += RL.proj[c][k] * x[k];
-                        y[c] = t;
-                    }
-#pragma unroll
-                    for (int c = 0; c < N1; ++c) s[c * N1 * N1] = y[c];
-                }
-                __syncthreads();
-            }
-            // derivative along d and time integral into the new modes
-#pragma unroll
-            for (int r = 0; r < S::TPL; ++r) {
-                const int t = lane + 64 * r;
-                if (t < S::NTGT) {
-                    const int z = t / (MT * NV), rem = t % (MT * NV), mt = rem / NV, v = rem % NV;
-                    const double* s = sr + z * SL + v * NS;
-                    double sum = 0.0;
-                    const int cnt = AT.n[d][mt];
-                    for (int q = 0; q < cnt; ++q)
-                        if (AT.ep[d][mt][q] < ne) sum += AT.coef[d][mt][q] * s[AT.off[d][mt][q]];
-                    acc[r] -= lam[d] * sum;
-                }
+        __syncthreads();
+        // ---- projection phase: one lane per slice
+        {
+            const int nsl = ZPW * ne * D * NV;
+            for (int s = lane; s < nsl; s += 64) {
+                const int z = s / (ne * D * NV), r = s % (ne * D * NV);
+                project_slice<D, P>(sr + (z * NSLZ + r) * RS);
             }
         }
         __syncthreads();
+        // ---- assembly: derivative along each axis and time integral
+        //   q[t] -= sum_d lam_d sum_e' I[e'][e_t] sum_{a'' > t_d} D[a''][t_d] f_{e',d}[.. a'' ..]
 #pragma unroll
         for (int r = 0; r < S::TPL; ++r) {
-            const int t = lane + 64 * r;
-            if (t < S::NTGT) {
-                const int z = t / (MT * NV), rem = t % (MT * NV), mt = rem / NV, v = rem % NV;
-                sq[(z * MST + MS + mt) * NV + v] = acc[r];
+            const Target& T = tg[r];
+            if (!T.valid) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                if (e >= ne || T.e > e + 1) continue;
+                double ci = 0.0;
+#pragma unroll
+                for (int et = 1; et <= P; ++et)
+                    if (T.e == et) ci = RL.I[e][et];
+                double sum = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int td = (d == 0) ? T.a : (d == 1 ? T.b : T.c);
+                    const int others = T.a + T.b + T.c - td;
+                    const double* f = sr + (T.z * NSLZ + (e * D + d) * NV + T.v) * RS;
+                    double sd = 0.0;
+#pragma unroll
+                    for (int hi = 1; hi <= P; ++hi) {
+                        if (hi > td && hi + others + e <= P) {
+                            double cd = 0.0;
+#pragma unroll
+                            for (int lo = 0; lo < P; ++lo)
+                                if (td == lo) cd = RL.D[hi][lo];
+                            const int ia = (d == 0) ? hi : T.a, ib = (d == 1) ? hi : T.b, ic = (d == 2) ? hi : T.c;
+                            const int off = (D == 3) ? (ic * N1 + ib) * N1 + ia : ib * N1 + ia;
+                            sd += cd * f[off];
+                        }
+                    }
+                    sum += lam[d] * sd;
+                }
+                acc += ci * sum;
             }
+            sq[(T.z * MST + MS + (lane + 64 * r) % (MT * NV) / NV) * NV + T.v] = -acc;
         }
         __syncthreads();
     }
