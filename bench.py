@@ -129,6 +129,28 @@ def cpu_baseline(order, seconds):
                       f"({el:.1f} s, OpenMP threads={threads})"}
 
 
+def mixed_run(hog, torch, pb, order, steps, ref):
+    """Same workload on the mixed path (FP32 reconstruction / predictor / face
+    states / Riemann solver, FP64 weights, face sum, update and CFL), timed the
+    same way; L1 against the FP64 path's state after the same steps (that path
+    matches the FP64 CPU oracle to 1e-12 relative L1 in the parity tests)."""
+    import numpy as np
+    g = hog.Grid.from_problem(pb, order, precision="mixed")
+    g.advance(2)
+    g.set_state(pb.U)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.advance(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    U = g.get_state()
+    rel = float(np.abs(U - ref).sum() / np.abs(ref).sum())
+    rho_l1 = float(np.abs(U[0] - ref[0]).mean())
+    g.close()
+    return {"value": pb.U[0].size * steps / el, "unit": UNIT, "ms_per_step": el * 1e3 / steps,
+            "dtype": "f32+f64", "rel_l1_vs_fp64": rel, "density_l1_vs_fp64": rho_l1}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +160,7 @@ def main():
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed FP32/FP64 comparison run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 2 x 1 GiB (known bytes) to "
                          "calibrate the FETCH_SIZE / WRITE_SIZE counters")
@@ -209,6 +232,8 @@ def main():
         "stages_ms_per_launch": stage_ms,
         "predictor_fraction_of_step": prof["predictor"][0] / args.steps / step_sum if step_sum > 0 else None,
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_run(hog, torch, pb, order, args.steps, g.get_state())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(order, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -49,7 +49,12 @@ enum {
 
 enum { HOG_PERIODIC = 0, HOG_OUTFLOW = 1 };            /* per-axis boundary */
 enum { HOG_HLLC = 0, HOG_HLL = 1, HOG_RUSANOV = 2 };   /* Riemann solver */
-enum { HOG_FP64 = 0 };                                 /* arithmetic of the path */
+/* Arithmetic of the path.  HOG_FP64: everything in FP64.  HOG_MIXED: the
+ * reconstruction coefficients, predictor, face states and Riemann solver in
+ * FP32; the stencil differences, smoothness indicators, epsilon division and
+ * nonlinear weights, the face-flux Gauss sum, the conservative update and the
+ * CFL reduction in FP64.  The state is FP64 on both paths. */
+enum { HOG_FP64 = 0, HOG_MIXED = 1 };
 enum { HOG_SOA = 0, HOG_AOS = 1 };                     /* state layouts */
 enum { HOG_HOST = 0, HOG_DEVICE = 1 };                 /* where a user buffer lives */
 
@@ -75,7 +80,7 @@ typedef struct hog_config {
     int order;           /* 3 or 4 (polynomial degree p = order - 1) */
     int riemann;         /* HOG_HLLC | HOG_HLL | HOG_RUSANOV */
     int bc[3];           /* per axis HOG_PERIODIC | HOG_OUTFLOW */
-    int precision;       /* HOG_FP64 */
+    int precision;       /* HOG_FP64 | HOG_MIXED */
     int linear_weno;     /* 1: WENO nonlinear weights replaced by the linear ones */
     int debug;           /* 1: keep the space-time modes for HOG_TAP_STMODES */
     int positivity;      /* 1: a zone whose predictor meets rho <= 0, p <= 0 or a

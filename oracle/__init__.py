@@ -66,6 +66,11 @@ def lib():
         L.oracle_step.restype = C.c_int
         L.oracle_step_count.argtypes = [cp, dp, C.c_double, dp, C.POINTER(C.c_longlong)]
         L.oracle_step_count.restype = C.c_int
+        up = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+        L.oracle_step_gated.argtypes = [cp, dp, C.c_double, up, dp, C.POINTER(C.c_longlong)]
+        L.oracle_step_gated.restype = C.c_int
+        L.oracle_zone_maxdev.argtypes = [cp, dp, dp]
+        L.oracle_zone_maxdev.restype = C.c_int
         L.oracle_step_zones.argtypes = [cp, dp, C.c_double, C.c_int, ip, dp]
         L.oracle_step_zones.restype = C.c_int
         L.oracle_cfl_dt.argtypes = [cp, dp, C.POINTER(C.c_longlong)]
@@ -161,6 +166,30 @@ def step_count(cfg, U, dt):
     if rc != 0:
         raise MemoryError("oracle_step failed")
     return out, n.value
+
+
+def step_gated(cfg, U, dt, gate):
+    """One step where the 1D WENO applications centred at zones with gate = 1
+    use the linear weights; gate has the interior shape (uint8)."""
+    U = _state(U)
+    g = np.ascontiguousarray(gate, dtype=np.uint8)
+    assert g.size == U[0].size
+    out = np.empty_like(U)
+    n = C.c_longlong(0)
+    rc = lib().oracle_step_gated(C.byref(cfg), U, float(dt), g.reshape(-1), out, C.byref(n))
+    if rc != 0:
+        raise MemoryError("oracle_step_gated failed")
+    return out, n.value
+
+
+def zone_maxdev(cfg, U):
+    """max_k |omega_k/gamma_k - 1| per interior zone (applications centred there)."""
+    U = _state(U)
+    out = np.empty(U[0].shape, dtype=np.float64)
+    rc = lib().oracle_zone_maxdev(C.byref(cfg), U, out.reshape(-1))
+    if rc != 0:
+        raise MemoryError("oracle_zone_maxdev failed")
+    return out
 
 
 def step_zones(cfg, U, dt, ijk):

@@ -270,7 +270,10 @@ void oracle_phys_flux(const ocfg *c, int dir, const double *U, double *F) { phys
 /* ------------------------------------------------------------------------ */
 /* Output c[1..p] are the undivided Legendre coefficients of the zone
  * polynomial c0 + c1 P1 + ... + cp Pp; the mean c0 = v0 is untouched. */
-void oracle_weno1d(const ocfg *cf, int p, const double *v5, double *out)
+/* linear: use the linear weights; dev (may be NULL): receives
+ * max_k |omega_k / gamma_k - 1| of the nonlinear weights (the smoothness
+ * measure the learned gate is trained to predict). */
+static void weno1d_core(const ocfg *cf, int p, const double *v5, int linear, double *out, double *dev)
 {
     const double *v = v5 + 2;   /* v[-2..2] */
     /* Quadratic candidates reproducing the averages of {-2,-1,0}, {-1,0,1}, {0,1,2}. */
@@ -288,13 +291,18 @@ void oracle_weno1d(const ocfg *cf, int p, const double *v5, double *out)
     out[0] = out[1] = out[2] = out[3] = 0.0;
     if (p == 2) {
         double wL, wC, wR;
-        if (cf->linear_weno) {
+        double aL = cf->g3[0] / ((eps + ISL) * (eps + ISL));
+        double aC = cf->g3[1] / ((eps + ISC) * (eps + ISC));
+        double aR = cf->g3[2] / ((eps + ISR) * (eps + ISR));
+        double s = aL + aC + aR;
+        if (dev) {
+            double d0 = fabs(aL / s / cf->g3[0] - 1.0), d1 = fabs(aC / s / cf->g3[1] - 1.0);
+            double d2 = fabs(aR / s / cf->g3[2] - 1.0);
+            *dev = fmax(d0, fmax(d1, d2));
+        }
+        if (linear) {
             wL = cf->g3[0]; wC = cf->g3[1]; wR = cf->g3[2];
         } else {
-            double aL = cf->g3[0] / ((eps + ISL) * (eps + ISL));
-            double aC = cf->g3[1] / ((eps + ISC) * (eps + ISC));
-            double aR = cf->g3[2] / ((eps + ISR) * (eps + ISR));
-            double s = aL + aC + aR;
             wL = aL / s; wC = aC / s; wR = aR / s;
         }
         out[1] = wL * L1 + wC * C1 + wR * R1;
@@ -310,14 +318,19 @@ void oracle_weno1d(const ocfg *cf, int p, const double *v5, double *out)
     double ISH = t * t + 13.0 / 3.0 * H2 * H2 + 781.0 / 20.0 * H3 * H3;
     double gH = cf->g4[0], gL = cf->g4[1], gC = cf->g4[2], gR = cf->g4[3];
     double wH, wL, wC, wR;
-    if (cf->linear_weno) {
+    double aH = gH / ((eps + ISH) * (eps + ISH));
+    double aL = gL / ((eps + ISL) * (eps + ISL));
+    double aC = gC / ((eps + ISC) * (eps + ISC));
+    double aR = gR / ((eps + ISR) * (eps + ISR));
+    double s = aH + aL + aC + aR;
+    if (dev) {
+        double d0 = fabs(aH / s / gH - 1.0), d1 = fabs(aL / s / gL - 1.0);
+        double d2 = fabs(aC / s / gC - 1.0), d3 = fabs(aR / s / gR - 1.0);
+        *dev = fmax(fmax(d0, d1), fmax(d2, d3));
+    }
+    if (linear) {
         wH = gH; wL = gL; wC = gC; wR = gR;
     } else {
-        double aH = gH / ((eps + ISH) * (eps + ISH));
-        double aL = gL / ((eps + ISL) * (eps + ISL));
-        double aC = gC / ((eps + ISC) * (eps + ISC));
-        double aR = gR / ((eps + ISR) * (eps + ISR));
-        double s = aH + aL + aC + aR;
         wH = aH / s; wL = aL / s; wC = aC / s; wR = aR / s;
     }
     double r = wH / gH;
@@ -326,13 +339,23 @@ void oracle_weno1d(const ocfg *cf, int p, const double *v5, double *out)
     out[3] = r * H3;
 }
 
+void oracle_weno1d(const ocfg *cf, int p, const double *v5, double *out)
+{
+    weno1d_core(cf, p, v5, cf->linear_weno, out, NULL);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Multi-D reconstruction of one zone by successive x -> y -> z sweeps        */
 /* ------------------------------------------------------------------------ */
 /* blk: nv * 5^d zone averages around the zone, index [v][dz][dy][dx] with
  * offsets -2..2 stored at 0..4 (2D: [v][dy][dx]).  W: spatial modes in the
  * st_modes order (e = 0 block), [mode][v]. */
-void oracle_recon_block(const ocfg *cf, const double *blk, double *W)
+/* fl (may be NULL): gate flags of the zones the x-sweep lines are centred at,
+ * [dz][dy] (2D: [dy]); an application centred at a flagged zone uses the
+ * linear weights.  maxdev (may be NULL): max_k |omega_k/gamma_k - 1| over all
+ * variables and all applications centred at the zone itself. */
+void oracle_recon_block_ex(const ocfg *cf, const double *blk, double *W, const unsigned char *fl,
+                           double *maxdev)
 {
     int nd = cf->ndim, nv = nd + 2, p = cf->order - 1;
     mode4 m[MAXST];
@@ -342,6 +365,9 @@ void oracle_recon_block(const ocfg *cf, const double *blk, double *W)
     int ms = 0;
     mode4 sm[MAXST];
     for (int i = 0; i < nst; ++i) if (m[i].e == 0) sm[ms++] = m[i];
+    int zc = (nd == 3) ? 2 : 0;                 /* z index of the zone itself */
+    double dmax = 0.0;
+#define FLAG(z, y) (cf->linear_weno || (fl && fl[(z) * 5 + (y)]))
     for (int v = 0; v < nv; ++v) {
         const double *b = blk + (size_t)v * nzb * 25;
         /* x sweep on every (dz, dy) line: A[a][dz][dy] */
@@ -350,7 +376,9 @@ void oracle_recon_block(const ocfg *cf, const double *blk, double *W)
             for (int y = 0; y < 5; ++y) {
                 double line[5], c[4];
                 for (int x = 0; x < 5; ++x) line[x] = b[(z * 5 + y) * 5 + x];
-                oracle_weno1d(cf, p, line, c);
+                double dv = 0.0;
+                weno1d_core(cf, p, line, FLAG(z, y), c, &dv);
+                if (z == zc && y == 2) dmax = fmax(dmax, dv);
                 A[0][z][y] = line[2];
                 for (int a = 1; a <= p; ++a) A[a][z][y] = c[a];
             }
@@ -362,7 +390,9 @@ void oracle_recon_block(const ocfg *cf, const double *blk, double *W)
                 for (int y = 0; y < 5; ++y) line[y] = A[a][z][y];
                 B[a][0][z] = line[2];
                 if (p - a >= 1) {
-                    oracle_weno1d(cf, p, line, c);
+                    double dv = 0.0;
+                    weno1d_core(cf, p, line, FLAG(z, 2), c, &dv);
+                    if (z == zc) dmax = fmax(dmax, dv);
                     for (int bb = 1; bb <= p - a; ++bb) B[a][bb][z] = c[bb];
                 }
             }
@@ -377,12 +407,21 @@ void oracle_recon_block(const ocfg *cf, const double *blk, double *W)
             } else {
                 double line[5], c[4];
                 for (int z = 0; z < 5; ++z) line[z] = B[a][bb][z];
-                oracle_weno1d(cf, p, line, c);
+                double dv = 0.0;
+                weno1d_core(cf, p, line, FLAG(2, 2), c, &dv);
+                dmax = fmax(dmax, dv);
                 val = c[cc];
             }
             W[k * nv + v] = val;
         }
     }
+#undef FLAG
+    if (maxdev) *maxdev = dmax;
+}
+
+void oracle_recon_block(const ocfg *cf, const double *blk, double *W)
+{
+    oracle_recon_block_ex(cf, blk, W, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -565,13 +604,31 @@ static void face_point(int nd, int dir, int side, int pt, double *x, double *tau
  * quadrature node, or whose final polynomial is inadmissible at any face
  * point, falls back to its zone mean (first order in space and time).
  * Returns 1 for such a zone. */
-static int zone_q(const ocfg *c, const grid_t *g, const double *P, const double *lam,
+/* gate (may be NULL): per interior zone [nz][ny][nx], 1 = the 1D applications
+ * centred at that zone use the linear weights; zones outside the interior
+ * always use the nonlinear ones. */
+static void gather_flags(const grid_t *g, const unsigned char *gate, int i, int j, int k, unsigned char *fl)
+{
+    int nzb = (g->nd == 3) ? 5 : 1;
+    memset(fl, 0, 25);
+    if (!gate) return;
+    for (int z = 0; z < nzb; ++z)
+        for (int y = 0; y < 5; ++y) {
+            int jj = j + y - 2, kk = (g->nd == 3) ? k + z - 2 : 0;
+            if (i < 0 || i >= g->n[0] || jj < 0 || jj >= g->n[1] || kk < 0 || kk >= g->n[2]) continue;
+            fl[z * 5 + y] = gate[((size_t)kk * g->n[1] + jj) * g->n[0] + i];
+        }
+}
+
+static int zone_q(const ocfg *c, const grid_t *g, const double *P, const double *lam, const unsigned char *gate,
                   int i, int j, int k, double *q)
 {
     double blk[MAXV * 125], W[MAXST * MAXV];
+    unsigned char fl[25];
     int nd = g->nd, nv = g->nv;
     gather_block(g, P, i, j, k, blk);
-    oracle_recon_block(c, blk, W);
+    gather_flags(g, gate, i, j, k, fl);
+    oracle_recon_block_ex(c, blk, W, fl, NULL);
     int bad = oracle_predict(c, lam, W, q);
     if (!c->positivity) return 0;
     mode4 m[MAXST];
@@ -653,16 +710,23 @@ double oracle_cfl_dt(const ocfg *c, const double *U, long long *bad)
 
 /* One ADER-WENO step of the whole grid with time step dt.  U, Unew: interior
  * SoA [nv][nz][ny][nx] (may not alias).  Returns 0, or -1 on allocation failure. */
-int oracle_step_count(const ocfg *c, const double *U, double dt, double *Unew, long long *ntroubled);
+int oracle_step_gated(const ocfg *c, const double *U, double dt, const unsigned char *gate, double *Unew,
+                      long long *ntroubled);
 int oracle_step(const ocfg *c, const double *U, double dt, double *Unew)
 {
     long long n;
-    return oracle_step_count(c, U, dt, Unew, &n);
+    return oracle_step_gated(c, U, dt, NULL, Unew, &n);
+}
+int oracle_step_count(const ocfg *c, const double *U, double dt, double *Unew, long long *ntroubled)
+{
+    return oracle_step_gated(c, U, dt, NULL, Unew, ntroubled);
 }
 
-/* One step; *ntroubled receives the number of zones of the predictor box
- * (interior grown by one zone per active axis) that used the fallback. */
-int oracle_step_count(const ocfg *c, const double *U, double dt, double *Unew, long long *ntroubled)
+/* One step; gate (may be NULL) as for zone_q; *ntroubled receives the number
+ * of zones of the predictor box (interior grown by one zone per active axis)
+ * that used the positivity fallback. */
+int oracle_step_gated(const ocfg *c, const double *U, double dt, const unsigned char *gate, double *Unew,
+                      long long *ntroubled)
 {
     grid_t g;
     grid_init(c, &g);
@@ -685,7 +749,7 @@ int oracle_step_count(const ocfg *c, const double *U, double dt, double *Unew, l
     for (int k = 0; k < e[2]; ++k)
         for (int j = 0; j < e[1]; ++j)
             for (int i = 0; i < e[0]; ++i)
-                nbad += zone_q(c, &g, P, lam, i - 1, j - 1, k - o3, Q + (((size_t)k * e[1] + j) * e[0] + i) * qs);
+                nbad += zone_q(c, &g, P, lam, gate, i - 1, j - 1, k - o3, Q + (((size_t)k * e[1] + j) * e[0] + i) * qs);
     *ntroubled = nbad;
 #define QAT(i, j, k) (Q + (((size_t)((k) + o3) * e[1] + ((j) + 1)) * e[0] + ((i) + 1)) * qs)
     size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
@@ -738,12 +802,12 @@ int oracle_step_zones(const ocfg *c, const double *U, double dt, int nlist, cons
         size_t z = ((size_t)k * g.n[1] + j) * g.n[0] + i;
         double u[MAXV];
         for (int v = 0; v < nv; ++v) u[v] = U[v * N + z];
-        zone_q(c, &g, P, lam, i, j, k, qc);
+        zone_q(c, &g, P, lam, NULL, i, j, k, qc);
         for (int d = 0; d < nd; ++d) {
             int o[3] = {0, 0, 0};
             o[d] = 1;
-            zone_q(c, &g, P, lam, i - o[0], j - o[1], k - o[2], qm);
-            zone_q(c, &g, P, lam, i + o[0], j + o[1], k + o[2], qp);
+            zone_q(c, &g, P, lam, NULL, i - o[0], j - o[1], k - o[2], qm);
+            zone_q(c, &g, P, lam, NULL, i + o[0], j + o[1], k + o[2], qp);
             face_flux(c, d, qm, qc, Fm);
             face_flux(c, d, qc, qp, Fp);
             for (int v = 0; v < nv; ++v) u[v] = u[v] - lam[d] * (Fp[v] - Fm[v]);
@@ -812,6 +876,27 @@ int oracle_stage_modes(const ocfg *c, const double *U, double dt, double *Wout, 
             oracle_predict(c, lam, W, q);
             memcpy(qout + (size_t)z * nst * nv, q, sizeof(double) * nst * nv);
         }
+    }
+    free(P);
+    return 0;
+}
+
+/* Per interior zone: max_k |omega_k/gamma_k - 1| over the variables and the
+ * 1D applications centred at the zone (full nonlinear weights). */
+int oracle_zone_maxdev(const ocfg *c, const double *U, double *out)
+{
+    grid_t g;
+    grid_init(c, &g);
+    double *P = make_padded(c, &g, U);
+    if (!P) return -1;
+    size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long long z = 0; z < (long long)N; ++z) {
+        int i = (int)(z % g.n[0]), j = (int)((z / g.n[0]) % g.n[1]), k = (int)(z / ((size_t)g.n[0] * g.n[1]));
+        double blk[MAXV * 125], W[MAXST * MAXV], d;
+        gather_block(&g, P, i, j, k, blk);
+        oracle_recon_block_ex(c, blk, W, NULL, &d);
+        out[z] = d;
     }
     free(P);
     return 0;

@@ -40,6 +40,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Plan {
     int nd, nv, p;
+    int es;          // bytes per element of the reconstruction / predictor arrays
     int n[3];
     Pad pad;
     Box I, AX, BY, R, FB[3];
@@ -60,7 +61,10 @@ int check_cfg(const hog_config* c)
     if (c->riemann < 0 || c->riemann > 2) return fail(HOG_EINVAL, "unknown Riemann solver %d", c->riemann);
     for (int d = 0; d < 3; ++d)
         if (c->bc[d] != HOG_PERIODIC && c->bc[d] != HOG_OUTFLOW) return fail(HOG_EINVAL, "bad boundary type on axis %d", d);
-    if (c->precision != HOG_FP64) return fail(HOG_EINVAL, "precision %d not supported", c->precision);
+    if (c->precision != HOG_FP64 && c->precision != HOG_MIXED)
+        return fail(HOG_EINVAL, "precision %d not supported", c->precision);
+    if (c->precision == HOG_MIXED && c->debug)
+        return fail(HOG_EINVAL, "space-time mode taps are kept on the FP64 path only");
     for (int i = 0; i < 3; ++i)
         if (c->reserved[i] != 0) return fail(HOG_EINVAL, "reserved fields must be 0");
     if (c->positivity != 0 && c->positivity != 1) return fail(HOG_EINVAL, "positivity must be 0 or 1");
@@ -90,6 +94,8 @@ void plan(const hog_config* c, Plan* P)
 {
     const int nd = c->ndim, p = c->order - 1, nv = nd + 2;
     P->nd = nd; P->nv = nv; P->p = p;
+    const size_t es = (c->precision == HOG_MIXED) ? sizeof(float) : sizeof(double);
+    P->es = (int)es;
     P->n[0] = c->nx; P->n[1] = c->ny; P->n[2] = (nd == 3) ? c->nz : 1;
     const int g3 = (nd == 3) ? kGhostZones : 0;
     P->pad.np[0] = P->n[0] + 2 * kGhostZones;
@@ -121,10 +127,10 @@ void plan(const hog_config* c, Plan* P)
     P->off_info = take(sizeof(StepInfo));
     P->off_U[0] = take(sizeof(double) * nv * P->pad.vs);
     P->off_U[1] = take(sizeof(double) * nv * P->pad.vs);
-    P->off_A = take(sizeof(double) * (p + 1) * nv * box_size(P->AX));
-    P->off_B = take(sizeof(double) * npairs * nv * box_size(P->BY));
-    P->off_W = (nd == 3) ? take(sizeof(double) * P->ms * nv * box_size(P->R)) : P->off_B;
-    P->off_FP = take(sizeof(double) * nd * 2 * npt * nv * box_size(P->R));
+    P->off_A = take(es * (p + 1) * nv * box_size(P->AX));
+    P->off_B = take(es * npairs * nv * box_size(P->BY));
+    P->off_W = (nd == 3) ? take(es * P->ms * nv * box_size(P->R)) : P->off_B;
+    P->off_FP = take(es * nd * 2 * npt * nv * box_size(P->R));
     for (int d = 0; d < 3; ++d) P->off_F[d] = (d < nd) ? take(sizeof(double) * nv * box_size(P->FB[d])) : 0;
     P->off_Q = c->debug ? take(sizeof(double) * P->mst * nv * box_size(P->R)) : 0;
     P->off_stage = take(sizeof(double) * nv * box_size(P->I));
@@ -146,7 +152,8 @@ struct hog_grid {
     double h[3];
     StepInfo* info;
     double* U[2];
-    double *A, *B, *W, *FP, *F[3], *Q, *stage;
+    void *A, *B, *W, *FP, *Q;     // element type: double (FP64) or float (mixed)
+    double *F[3], *stage;
     // stage timing: pairs of events per recorded stage launch, evaluated on read
     bool profiling;
     std::vector<hipEvent_t> ev_pool;
@@ -197,9 +204,14 @@ int launch_check(const char* what)
     return HOG_OK;
 }
 
-template <int D, int P>
+template <int D, int P, typename T>
 int enqueue_step_t(hog_grid* g, double dt_user)
 {
+    T* A = static_cast<T*>(g->A);
+    T* B = static_cast<T*>(g->B);
+    T* W = static_cast<T*>(g->W);
+    T* FPa = static_cast<T*>(g->FP);
+    T* Q = static_cast<T*>(g->Q);
     const Plan& L = g->P;
     hipStream_t s = g->stream;
     const double* h = g->h;
@@ -214,22 +226,22 @@ int enqueue_step_t(hog_grid* g, double dt_user)
     }
     {
         StageMark m(g, 1);
-        k_recon_x<D, P><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, g->A, g->wa);
-        k_recon_y<D, P><<<nblocks(box_size(L.BY), 256), 256, 0, s>>>(g->A, L.AX, L.BY, g->B, g->wa);
+        k_recon_x<D, P, T><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa);
+        k_recon_y<D, P, T><<<nblocks(box_size(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa);
         if constexpr (D == 3)
-            k_recon_z<P><<<nblocks(box_size(L.R), 256), 256, 0, s>>>(g->B, L.BY, L.R, g->W, g->wa);
+            k_recon_z<P, T><<<nblocks(box_size(L.R), 256), 256, 0, s>>>(B, L.BY, L.R, W, g->wa);
     }
     {
         StageMark m(g, 2);
         using S = PredShape<D, P>;
         const long long ngroups = (box_size(L.R) + S::ZPW - 1) / S::ZPW;
-        k_predict<D, P><<<xcd_blocks(ngroups), 64, 0, s>>>(g->W, L.R, g->info, g->cfg.gamma, g->cfg.positivity,
-                                                            g->FP, g->Q);
+        k_predict<D, P, T><<<xcd_blocks(ngroups), 64, 0, s>>>(W, L.R, g->info, g->cfg.gamma, g->cfg.positivity,
+                                                               FPa, Q);
     }
     {
         StageMark m(g, 3);
         for (int d = 0; d < D; ++d)
-            k_riemann<D><<<nblocks(box_size(L.FB[d]), 256), 256, 0, s>>>(g->FP, L.R, L.FB[d], d, g->cfg.riemann,
+            k_riemann<D, T><<<nblocks(box_size(L.FB[d]), 256), 256, 0, s>>>(FPa, L.R, L.FB[d], d, g->cfg.riemann,
                                                                           g->cfg.gamma, g->F[d]);
     }
     {
@@ -243,12 +255,16 @@ int enqueue_step_t(hog_grid* g, double dt_user)
 
 int enqueue_step(hog_grid* g, double dt_user)
 {
-    const int key = g->P.nd * 10 + g->P.p;
+    const int key = (g->cfg.precision == HOG_MIXED ? 100 : 0) + g->P.nd * 10 + g->P.p;
     switch (key) {
-    case 22: return enqueue_step_t<2, 2>(g, dt_user);
-    case 23: return enqueue_step_t<2, 3>(g, dt_user);
-    case 32: return enqueue_step_t<3, 2>(g, dt_user);
-    case 33: return enqueue_step_t<3, 3>(g, dt_user);
+    case 22: return enqueue_step_t<2, 2, double>(g, dt_user);
+    case 23: return enqueue_step_t<2, 3, double>(g, dt_user);
+    case 32: return enqueue_step_t<3, 2, double>(g, dt_user);
+    case 33: return enqueue_step_t<3, 3, double>(g, dt_user);
+    case 122: return enqueue_step_t<2, 2, float>(g, dt_user);
+    case 123: return enqueue_step_t<2, 3, float>(g, dt_user);
+    case 132: return enqueue_step_t<3, 2, float>(g, dt_user);
+    case 133: return enqueue_step_t<3, 3, float>(g, dt_user);
     }
     return fail(HOG_EINVAL, "unsupported dimension/order");
 }
@@ -346,12 +362,12 @@ int hog_create(const hog_config* cfg, void* workspace, size_t bytes, void* hip_s
     g->info = reinterpret_cast<StepInfo*>(g->ws + P.off_info);
     g->U[0] = reinterpret_cast<double*>(g->ws + P.off_U[0]);
     g->U[1] = reinterpret_cast<double*>(g->ws + P.off_U[1]);
-    g->A = reinterpret_cast<double*>(g->ws + P.off_A);
-    g->B = reinterpret_cast<double*>(g->ws + P.off_B);
-    g->W = reinterpret_cast<double*>(g->ws + P.off_W);
-    g->FP = reinterpret_cast<double*>(g->ws + P.off_FP);
+    g->A = g->ws + P.off_A;
+    g->B = g->ws + P.off_B;
+    g->W = g->ws + P.off_W;
+    g->FP = g->ws + P.off_FP;
     for (int d = 0; d < 3; ++d) g->F[d] = (d < P.nd) ? reinterpret_cast<double*>(g->ws + P.off_F[d]) : nullptr;
-    g->Q = cfg->debug ? reinterpret_cast<double*>(g->ws + P.off_Q) : nullptr;
+    g->Q = cfg->debug ? static_cast<void*>(g->ws + P.off_Q) : nullptr;
     g->stage = reinterpret_cast<double*>(g->ws + P.off_stage);
     k_reset<<<1, 1, 0, g->stream>>>(g->info, 0.0, 1);
     rc = launch_check("reset");
@@ -573,12 +589,17 @@ int hog_debug_tap(hog_grid* g, int tap, void* dst, size_t bytes)
     const int nv = L.nv;
     if (tap == HOG_TAP_MODES || tap == HOG_TAP_STMODES) {
         const int nm = (tap == HOG_TAP_MODES) ? L.ms : L.mst;
-        const double* src = (tap == HOG_TAP_MODES) ? g->W : g->Q;
+        const void* src = (tap == HOG_TAP_MODES) ? g->W : g->Q;
         if (!src) return fail(HOG_EINVAL, "space-time modes are kept only with debug = 1");
         if (bytes < sizeof(double) * N * nm * nv) return fail(HOG_EINVAL, "tap buffer too small");
-        std::vector<double> h((size_t)nm * nv * nR);
-        HIP_TRY(hipMemcpyAsync(h.data(), src, sizeof(double) * h.size(), hipMemcpyDeviceToHost, g->stream));
+        const size_t n = (size_t)nm * nv * nR;
+        std::vector<char> h(n * L.es);
+        HIP_TRY(hipMemcpyAsync(h.data(), src, h.size(), hipMemcpyDeviceToHost, g->stream));
         HIP_TRY(hipStreamSynchronize(g->stream));
+        auto at = [&](size_t i) {
+            return L.es == 8 ? reinterpret_cast<const double*>(h.data())[i]
+                             : (double)reinterpret_cast<const float*>(h.data())[i];
+        };
         double* out = static_cast<double*>(dst);
         for (int k = 0; k < L.n[2]; ++k)
             for (int j = 0; j < L.n[1]; ++j)
@@ -587,7 +608,7 @@ int hog_debug_tap(hog_grid* g, int tap, void* dst, size_t bytes)
                     const long long r = ((long long)(k - L.R.lo[2]) * L.R.n[1] + (j - L.R.lo[1])) * L.R.n[0] +
                                         (i - L.R.lo[0]);
                     for (int m = 0; m < nm; ++m)
-                        for (int v = 0; v < nv; ++v) out[(z * nm + m) * nv + v] = h[((size_t)m * nv + v) * nR + r];
+                        for (int v = 0; v < nv; ++v) out[(z * nm + m) * nv + v] = at(((size_t)m * nv + v) * nR + r);
                 }
         return HOG_OK;
     }

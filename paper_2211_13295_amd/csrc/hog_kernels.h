@@ -179,9 +179,18 @@ __global__ __launch_bounds__(256) void k_cfl(const double* __restrict__ U, Pad p
 // ------------------------------------------------------------------------
 // a2: WENO reconstruction by successive 1D sweeps x -> y -> z.
 // ------------------------------------------------------------------------
-template <int D, int P>
+// Reconstruction of one 5-zone line in the arithmetic of the path: FP64, or
+// the mixed path's FP32 coefficients with FP64 weights.
+template <int P, typename T>
+__device__ __forceinline__ void weno_line(const double* line, T* c, const WenoArgs& wa)
+{
+    if constexpr (sizeof(T) == 8) weno1d<P>(line, c, wa);
+    else weno1d_mixed<P>(line, c, wa);
+}
+
+template <int D, int P, typename T>
 __global__ __launch_bounds__(256) void k_recon_x(const double* __restrict__ U, Pad p, Box AX,
-                                                 double* __restrict__ A, WenoArgs wa)
+                                                 T* __restrict__ A, WenoArgs wa)
 {
     constexpr int NV = D + 2;
     const long long nA = box_size(AX);
@@ -192,19 +201,20 @@ __global__ __launch_bounds__(256) void k_recon_x(const double* __restrict__ U, P
     const long long base = pad_index(p, i, j, k);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        double line[5], c[P + 1];
+        double line[5];
+        T c[P + 1];
 #pragma unroll
         for (int o = 0; o < 5; ++o) line[o] = U[v * p.vs + base + (o - 2)];
-        weno1d<P>(line, c, wa);
-        A[(0 * NV + v) * nA + z] = line[2];
+        weno_line<P, T>(line, c, wa);
+        A[(0 * NV + v) * nA + z] = (T)line[2];
 #pragma unroll
         for (int a = 1; a <= P; ++a) A[(a * NV + v) * nA + z] = c[a];
     }
 }
 
-template <int D, int P>
-__global__ __launch_bounds__(256) void k_recon_y(const double* __restrict__ A, Box AX, Box BY,
-                                                 double* __restrict__ B, WenoArgs wa)
+template <int D, int P, typename T>
+__global__ __launch_bounds__(256) void k_recon_y(const T* __restrict__ A, Box AX, Box BY,
+                                                 T* __restrict__ B, WenoArgs wa)
 {
     constexpr int NV = D + 2;
     constexpr Pairs<P> PR{};
@@ -219,21 +229,22 @@ __global__ __launch_bounds__(256) void k_recon_y(const double* __restrict__ A, B
     for (int a = 0; a <= P; ++a)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double line[5], c[P + 1];
+            double line[5];
+            T c[P + 1];
 #pragma unroll
-            for (int o = 0; o < 5; ++o) line[o] = A[(a * NV + v) * nA + c0 + (o - 2) * sy];
-            B[(PR.at[a][0] * NV + v) * nB + z] = line[2];
+            for (int o = 0; o < 5; ++o) line[o] = (double)A[(a * NV + v) * nA + c0 + (o - 2) * sy];
+            B[(PR.at[a][0] * NV + v) * nB + z] = (T)line[2];
             if (P - a >= 1) {
-                weno1d<P>(line, c, wa);
+                weno_line<P, T>(line, c, wa);
 #pragma unroll
                 for (int b = 1; b <= P - a; ++b) B[(PR.at[a][b] * NV + v) * nB + z] = c[b];
             }
         }
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_recon_z(const double* __restrict__ B, Box BY, Box R,
-                                                 double* __restrict__ W, WenoArgs wa)
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_recon_z(const T* __restrict__ B, Box BY, Box R,
+                                                 T* __restrict__ W, WenoArgs wa)
 {
     constexpr int NV = 5;
     constexpr Modes<3, P> M{};
@@ -251,12 +262,13 @@ __global__ __launch_bounds__(256) void k_recon_z(const double* __restrict__ B, B
         for (int a = 0; a + b <= P; ++a)
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                double line[5], c[P + 1];
+                double line[5];
+                T c[P + 1];
 #pragma unroll
-                for (int o = 0; o < 5; ++o) line[o] = B[(PR.at[a][b] * NV + v) * nB + c0 + (o - 2) * sz];
-                W[(M.at[a][b][0][0] * NV + v) * nR + z] = line[2];
+                for (int o = 0; o < 5; ++o) line[o] = (double)B[(PR.at[a][b] * NV + v) * nB + c0 + (o - 2) * sz];
+                W[(M.at[a][b][0][0] * NV + v) * nR + z] = (T)line[2];
                 if (P - a - b >= 1) {
-                    weno1d<P>(line, c, wa);
+                    weno_line<P, T>(line, c, wa);
 #pragma unroll
                     for (int cc = 1; cc <= P - a - b; ++cc) W[(M.at[a][b][cc][0] * NV + v) * nR + z] = c[cc];
                 }
@@ -319,39 +331,39 @@ struct Target {
 // (k*N1 + j)*N1 + i) -> modal coefficients written back to
 // row[(c*N1 + b)*N1 + a] for a + b + c <= P.  The node planes are streamed
 // (k outermost) into the modal accumulators, so only one plane is live.
-template <int D, int P>
-__device__ __forceinline__ void project_slice(double* row)
+template <int D, int P, typename T>
+__device__ __forceinline__ void project_slice(T* row)
 {
     constexpr int N1 = P + 1;
     constexpr Rules<P> RL{};
     if constexpr (D == 3) {
-        double out[N1][N1][N1] = {};   // [c][b][a], a + b + c <= P used
+        T out[N1][N1][N1] = {};   // [c][b][a], a + b + c <= P used
 #pragma unroll
         for (int k = 0; k < N1; ++k) {
-            double x[N1][N1];
+            T x[N1][N1];
 #pragma unroll
             for (int j = 0; j < N1; ++j)
 #pragma unroll
                 for (int i = 0; i < N1; ++i) x[j][i] = row[(k * N1 + j) * N1 + i];
-            double t1[N1][N1];   // [j][a]
+            T t1[N1][N1];   // [j][a]
 #pragma unroll
             for (int j = 0; j < N1; ++j)
 #pragma unroll
                 for (int a = 0; a <= P; ++a) {
-                    double s = 0.0;
+                    T s = T(0);
 #pragma unroll
-                    for (int i = 0; i < N1; ++i) s += RL.proj[a][i] * x[j][i];
+                    for (int i = 0; i < N1; ++i) s += T(RL.proj[a][i]) * x[j][i];
                     t1[j][a] = s;
                 }
 #pragma unroll
             for (int a = 0; a <= P; ++a)
 #pragma unroll
                 for (int b = 0; a + b <= P; ++b) {
-                    double s = 0.0;
+                    T s = T(0);
 #pragma unroll
-                    for (int j = 0; j < N1; ++j) s += RL.proj[b][j] * t1[j][a];
+                    for (int j = 0; j < N1; ++j) s += T(RL.proj[b][j]) * t1[j][a];
 #pragma unroll
-                    for (int c = 0; a + b + c <= P; ++c) out[c][b][a] += RL.proj[c][k] * s;
+                    for (int c = 0; a + b + c <= P; ++c) out[c][b][a] += T(RL.proj[c][k]) * s;
                 }
         }
 #pragma unroll
@@ -361,37 +373,37 @@ __device__ __forceinline__ void project_slice(double* row)
 #pragma unroll
                 for (int c = 0; a + b + c <= P; ++c) row[(c * N1 + b) * N1 + a] = out[c][b][a];
     } else {
-        double x[N1][N1];
+        T x[N1][N1];
 #pragma unroll
         for (int j = 0; j < N1; ++j)
 #pragma unroll
             for (int i = 0; i < N1; ++i) x[j][i] = row[j * N1 + i];
-        double t1[N1][N1];       // [j][a]
+        T t1[N1][N1];       // [j][a]
 #pragma unroll
         for (int j = 0; j < N1; ++j)
 #pragma unroll
             for (int a = 0; a <= P; ++a) {
-                double s = 0.0;
+                T s = T(0);
 #pragma unroll
-                for (int i = 0; i < N1; ++i) s += RL.proj[a][i] * x[j][i];
+                for (int i = 0; i < N1; ++i) s += T(RL.proj[a][i]) * x[j][i];
                 t1[j][a] = s;
             }
 #pragma unroll
         for (int a = 0; a <= P; ++a)
 #pragma unroll
             for (int b = 0; a + b <= P; ++b) {
-                double s = 0.0;
+                T s = T(0);
 #pragma unroll
-                for (int j = 0; j < N1; ++j) s += RL.proj[b][j] * t1[j][a];
+                for (int j = 0; j < N1; ++j) s += T(RL.proj[b][j]) * t1[j][a];
                 row[b * N1 + a] = s;
             }
     }
 }
 
-template <int D, int P>
-__global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W, Box R,
-                                                StepInfo* __restrict__ info, double gamma, int positivity,
-                                                double* __restrict__ FP, double* __restrict__ Qout)
+template <int D, int P, typename T>
+__global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box R,
+                                                   StepInfo* __restrict__ info, double gamma, int positivity,
+                                                   T* __restrict__ FP, T* __restrict__ Qout)
 {
     using S = PredShape<D, P>;
     constexpr int NV = S::NV, N1 = S::N1, NS = S::NS, ZPW = S::ZPW, RS = S::RS;
@@ -399,8 +411,8 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
     constexpr Modes<D, P> M{};
     constexpr Rules<P> RL{};
 
-    __shared__ double sq[ZPW * MST * NV];
-    __shared__ double sr[ZPW * NSLZ * RS];
+    __shared__ T sq[ZPW * MST * NV];
+    __shared__ T sr[ZPW * NSLZ * RS];
     __shared__ int sbad[ZPW];
 
     const long long nR = box_size(R);
@@ -409,8 +421,8 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
     if (grp >= ngroups) return;                       // whole wavefront, before any barrier
     const int lane = threadIdx.x;
     const long long zbase = (long long)grp * ZPW;
-    const double gm1 = gamma - 1.0;
-    const double lam[3] = {info->lam[0], info->lam[1], info->lam[2]};
+    const T gm1 = T(gamma - 1.0);
+    const T lam[3] = {T(info->lam[0]), T(info->lam[1]), T(info->lam[2])};
 
     for (int t = lane; t < ZPW * MST * NV; t += 64) {
         const int z = t / (MST * NV), r = t % (MST * NV), m = r / NV, v = r % NV;
@@ -423,14 +435,14 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
     const int node = lane % NS;
     const bool active = zs < ZPW;
     const int ii = node % N1, jj = (node / N1) % N1, kk = (D == 3) ? node / (N1 * N1) : 0;
-    double px[P + 1], py[P + 1], pz[P + 1];
+    T px[P + 1], py[P + 1], pz[P + 1];
     {
         const double xn = gl_node(N1, ii), yn = gl_node(N1, jj), zn = gl_node(N1, kk);
 #pragma unroll
         for (int a = 0; a <= P; ++a) {
-            px[a] = mleg(a, xn);
-            py[a] = mleg(a, yn);
-            pz[a] = (D == 3) ? mleg(a, zn) : (a == 0 ? 1.0 : 0.0);
+            px[a] = T(mleg(a, xn));
+            py[a] = T(mleg(a, yn));
+            pz[a] = (D == 3) ? T(mleg(a, zn)) : T(a == 0 ? 1 : 0);
         }
     }
     // the new-mode targets this lane accumulates
@@ -456,14 +468,14 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
     __syncthreads();
 
     // time-independent part of q at this lane's node (the reconstruction)
-    double Q0[NV];
+    T Q0[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Q0[v] = 0.0;
+    for (int v = 0; v < NV; ++v) Q0[v] = T(0);
     if (active) {
-        const double* qz = sq + zs * MST * NV;
+        const T* qz = sq + zs * MST * NV;
 #pragma unroll
         for (int m = 0; m < MS; ++m) {
-            const double phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
+            const T phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
 #pragma unroll
             for (int v = 0; v < NV; ++v) Q0[v] += qz[m * NV + v] * phi;
         }
@@ -475,52 +487,52 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
         // ---- node phase
         if (active) {
             bool ok = true;
-            double* rz = sr + zs * NSLZ * RS + node;     // slice (e, d, v) at rz[((e*D + d)*NV + v)*RS]
+            T* rz = sr + zs * NSLZ * RS + node;     // slice (e, d, v) at rz[((e*D + d)*NV + v)*RS]
             if (first) {
-                double F[D][NV];
-                ok = fluxes<D>(Q0, gm1, F);
+                T F[D][NV];
+                ok = fluxes<D, T>(Q0, gm1, F);
 #pragma unroll
                 for (int d = 0; d < D; ++d)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) rz[(d * NV + v) * RS] = F[d][v];
             } else {
-                double Qe[P][NV];                        // time modes e = 1..P at the node
+                T Qe[P][NV];                        // time modes e = 1..P at the node
 #pragma unroll
                 for (int e = 0; e < P; ++e)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) Qe[e][v] = 0.0;
-                const double* qz = sq + zs * MST * NV;
+                    for (int v = 0; v < NV; ++v) Qe[e][v] = T(0);
+                const T* qz = sq + zs * MST * NV;
 #pragma unroll
                 for (int m = MS; m < MST; ++m) {
-                    const double phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
+                    const T phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) Qe[M.e[m] - 1][v] += qz[m * NV + v] * phi;
                 }
-                double Racc[NE][D][NV];
+                T Racc[NE][D][NV];
 #pragma unroll
                 for (int e = 0; e < NE; ++e)
 #pragma unroll
                     for (int d = 0; d < D; ++d)
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) Racc[e][d][v] = 0.0;
+                        for (int v = 0; v < NV; ++v) Racc[e][d][v] = T(0);
 #pragma unroll
                 for (int l = 0; l < N1; ++l) {
-                    double U[NV];
+                    T U[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        double s = Qe[P - 1][v];
+                        T s = Qe[P - 1][v];
 #pragma unroll
-                        for (int e = P - 2; e >= 0; --e) s = s * RL.t[l] + Qe[e][v];
-                        U[v] = Q0[v] + s * RL.t[l];
+                        for (int e = P - 2; e >= 0; --e) s = s * T(RL.t[l]) + Qe[e][v];
+                        U[v] = Q0[v] + s * T(RL.t[l]);
                     }
-                    double F[D][NV];
-                    ok = fluxes<D>(U, gm1, F) && ok;
+                    T F[D][NV];
+                    ok = fluxes<D, T>(U, gm1, F) && ok;
 #pragma unroll
                     for (int e = 0; e < NE; ++e)
 #pragma unroll
                         for (int d = 0; d < D; ++d)
 #pragma unroll
-                            for (int v = 0; v < NV; ++v) Racc[e][d][v] += RL.tproj[e][l] * F[d][v];
+                            for (int v = 0; v < NV; ++v) Racc[e][d][v] += T(RL.tproj[e][l]) * F[d][v];
                 }
 #pragma unroll
                 for (int e = 0; e < NE; ++e)
@@ -537,7 +549,7 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
             const int nsl = ZPW * ne * D * NV;
             for (int s = lane; s < nsl; s += 64) {
                 const int z = s / (ne * D * NV), r = s % (ne * D * NV);
-                project_slice<D, P>(sr + (z * NSLZ + r) * RS);
+                project_slice<D, P, T>(sr + (z * NSLZ + r) * RS);
             }
         }
         __syncthreads();
@@ -545,31 +557,31 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
         //   q[t] -= sum_d lam_d sum_e' I[e'][e_t] sum_{a'' > t_d} D[a''][t_d] f_{e',d}[.. a'' ..]
 #pragma unroll
         for (int r = 0; r < S::TPL; ++r) {
-            const Target& T = tg[r];
-            if (!T.valid) continue;
-            double acc = 0.0;
+            const Target& tq = tg[r];
+            if (!tq.valid) continue;
+            T acc = T(0);
 #pragma unroll
             for (int e = 0; e < NE; ++e) {
-                if (e >= ne || T.e > e + 1) continue;
-                double ci = 0.0;
+                if (e >= ne || tq.e > e + 1) continue;
+                T ci = T(0);
 #pragma unroll
                 for (int et = 1; et <= P; ++et)
-                    if (T.e == et) ci = RL.I[e][et];
-                double sum = 0.0;
+                    if (tq.e == et) ci = T(RL.I[e][et]);
+                T sum = T(0);
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    const int td = (d == 0) ? T.a : (d == 1 ? T.b : T.c);
-                    const int others = T.a + T.b + T.c - td;
-                    const double* f = sr + (T.z * NSLZ + (e * D + d) * NV + T.v) * RS;
-                    double sd = 0.0;
+                    const int td = (d == 0) ? tq.a : (d == 1 ? tq.b : tq.c);
+                    const int others = tq.a + tq.b + tq.c - td;
+                    const T* f = sr + (tq.z * NSLZ + (e * D + d) * NV + tq.v) * RS;
+                    T sd = T(0);
 #pragma unroll
                     for (int hi = 1; hi <= P; ++hi) {
                         if (hi > td && hi + others + e <= P) {
-                            double cd = 0.0;
+                            T cd = T(0);
 #pragma unroll
                             for (int lo = 0; lo < P; ++lo)
-                                if (td == lo) cd = RL.D[hi][lo];
-                            const int ia = (d == 0) ? hi : T.a, ib = (d == 1) ? hi : T.b, ic = (d == 2) ? hi : T.c;
+                                if (td == lo) cd = T(RL.D[hi][lo]);
+                            const int ia = (d == 0) ? hi : tq.a, ib = (d == 1) ? hi : tq.b, ic = (d == 2) ? hi : tq.c;
                             const int off = (D == 3) ? (ic * N1 + ib) * N1 + ia : ib * N1 + ia;
                             sd += cd * f[off];
                         }
@@ -578,7 +590,7 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
                 }
                 acc += ci * sum;
             }
-            sq[(T.z * MST + MS + (lane + 64 * r) % (MT * NV) / NV) * NV + T.v] = -acc;
+            sq[(tq.z * MST + MS + (lane + 64 * r) % (MT * NV) / NV) * NV + tq.v] = -acc;
         }
         __syncthreads();
     }
@@ -593,9 +605,9 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
     // face-point states: side 0 at xi_d = -1/2, side 1 at +1/2; point index
     // (time, first tangential axis[, second tangential axis]) with time slowest.
     // A zone with an inadmissible node or face state falls back to its mean.
-    constexpr double g = 0.28867513459481288225;
+    constexpr T g = T(0.28867513459481288225);
     constexpr int FPL = (ZPW * S::NFPZ + 63) / 64;    // face points per lane
-    double Ufp[FPL][NV];
+    T Ufp[FPL][NV];
 #pragma unroll
     for (int r = 0; r < FPL; ++r) {
         const int t = lane + 64 * r;
@@ -606,33 +618,33 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
         int lt, a1, a2 = 0;
         if (D == 3) { lt = pt >> 2; a1 = (pt >> 1) & 1; a2 = pt & 1; }
         else { lt = pt >> 1; a1 = pt & 1; }
-        const double xn = side ? 0.5 : -0.5;
-        const double x1 = a1 ? g : -g, x2 = a2 ? g : -g;
+        const T xn = side ? T(0.5) : T(-0.5);
+        const T x1 = a1 ? g : -g, x2 = a2 ? g : -g;
         // axis ax gets the normal coordinate, the first or the second tangential one
-        const double cx = (d == 0) ? xn : x1;
-        const double cy = (d == 1) ? xn : (t1 == 1 ? x1 : x2);
-        const double cz = (D == 3) ? ((d == 2) ? xn : x2) : 0.0;
-        const double tau = 0.5 + (lt ? g : -g);
-        double bx[P + 1], by[P + 1], bz[P + 1], bt[P + 1];
+        const T cx = (d == 0) ? xn : x1;
+        const T cy = (d == 1) ? xn : (t1 == 1 ? x1 : x2);
+        const T cz = (D == 3) ? ((d == 2) ? xn : x2) : 0.0;
+        const T tau = T(0.5) + (lt ? g : -g);
+        T bx[P + 1], by[P + 1], bz[P + 1], bt[P + 1];
 #pragma unroll
         for (int a = 0; a <= P; ++a) {
-            bx[a] = mleg(a, cx);
-            by[a] = mleg(a, cy);
-            bz[a] = mleg(a, cz);
+            bx[a] = T(mleg(a, (double)cx));
+            by[a] = T(mleg(a, (double)cy));
+            bz[a] = T(mleg(a, (double)cz));
         }
-        bt[0] = 1.0;
+        bt[0] = T(1);
 #pragma unroll
         for (int e = 1; e <= P; ++e) bt[e] = bt[e - 1] * tau;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Ufp[r][v] = 0.0;
-        const double* qz = sq + z * MST * NV;
+        for (int v = 0; v < NV; ++v) Ufp[r][v] = T(0);
+        const T* qz = sq + z * MST * NV;
 #pragma unroll
         for (int m = 0; m < MST; ++m) {
-            const double phi = bx[M.a[m]] * by[M.b[m]] * bz[M.c[m]] * bt[M.e[m]];
+            const T phi = bx[M.a[m]] * by[M.b[m]] * bz[M.c[m]] * bt[M.e[m]];
 #pragma unroll
             for (int v = 0; v < NV; ++v) Ufp[r][v] += qz[m * NV + v] * phi;
         }
-        if (positivity && !admissible<D>(Ufp[r], gm1)) atomicOr(&sbad[z], 1);
+        if (positivity && !admissible<D, T>(Ufp[r], gm1)) atomicOr(&sbad[z], 1);
     }
     __syncthreads();
 #pragma unroll
@@ -656,10 +668,10 @@ __global__ __launch_bounds__(64, 2) void k_predict(const double* __restrict__ W,
 
 // ------------------------------------------------------------------------
 // a5: Riemann solver at the face Gauss points and the space-time average of
-// the face flux.  One thread per face along axis dir.
+// the face flux (always summed in FP64).  One thread per face along axis dir.
 // ------------------------------------------------------------------------
-template <int D>
-__global__ __launch_bounds__(256) void k_riemann(const double* __restrict__ FP, Box R, Box FB, int dir,
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_riemann(const T* __restrict__ FP, Box R, Box FB, int dir,
                                                  int solver, double gamma, double* __restrict__ F)
 {
     constexpr int NV = D + 2;
@@ -677,15 +689,15 @@ __global__ __launch_bounds__(256) void k_riemann(const double* __restrict__ FP, 
     constexpr double w = 1.0 / NPT;
 #pragma unroll
     for (int pt = 0; pt < NPT; ++pt) {
-        double UL[NV], UR[NV], Fp[NV];
+        T UL[NV], UR[NV], Fp[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             UL[v] = FP[((long long)((dir * 2 + 1) * NPT + pt) * NV + v) * nR + zl];
             UR[v] = FP[((long long)((dir * 2 + 0) * NPT + pt) * NV + v) * nR + zr];
         }
-        riemann<D>(UL, UR, dir, solver, gamma, Fp);
+        riemann<D, T>(UL, UR, dir, solver, T(gamma), Fp);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Fb[v] += w * Fp[v];
+        for (int v = 0; v < NV; ++v) Fb[v] += w * (double)Fp[v];     // face average in FP64
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v * nF + f] = Fb[v];

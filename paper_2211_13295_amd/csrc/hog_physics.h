@@ -14,60 +14,63 @@ struct WenoArgs {
     int linear;      // 1: weights fixed to the linear ones
 };
 
+// The device routines below are templates on the arithmetic type T: double
+// on the FP64 path, float where the mixed path computes in FP32.
+
 // Pressure of an ideal gas from the conserved variables of D dimensions.
-template <int D>
-__device__ __forceinline__ double pressure(const double* U, double gm1)
+template <int D, typename T = double>
+__device__ __forceinline__ T pressure(const T* U, T gm1)
 {
-    double ke = 0.0;
+    T ke = T(0);
 #pragma unroll
     for (int d = 0; d < D; ++d) ke += U[1 + d] * U[1 + d];
-    return gm1 * (U[D + 1] - 0.5 * ke / U[0]);
+    return gm1 * (U[D + 1] - T(0.5) * ke / U[0]);
 }
 
 // rho > 0, p > 0 and both finite.
-template <int D>
-__device__ __forceinline__ bool admissible(const double* U, double gm1)
+template <int D, typename T = double>
+__device__ __forceinline__ bool admissible(const T* U, T gm1)
 {
-    const double p = pressure<D>(U, gm1);
-    return U[0] > 0.0 && p > 0.0 && isfinite(U[0]) && isfinite(p);
+    const T p = pressure<D, T>(U, gm1);
+    return U[0] > T(0) && p > T(0) && isfinite(U[0]) && isfinite(p);
 }
 
 // Physical fluxes of the Euler equations along all D axes at one point;
 // returns whether the state is admissible (rho > 0, p > 0, finite).
-template <int D>
-__device__ __forceinline__ bool fluxes(const double* U, double gm1, double (*F)[D + 2])
+template <int D, typename T = double>
+__device__ __forceinline__ bool fluxes(const T* U, T gm1, T (*F)[D + 2])
 {
-    const double rho = U[0];
-    const double ir = 1.0 / rho;
-    double u[D];
-    double ke = 0.0;
+    const T rho = U[0];
+    const T ir = T(1) / rho;
+    T u[D];
+    T ke = T(0);
 #pragma unroll
     for (int d = 0; d < D; ++d) { u[d] = U[1 + d] * ir; ke += U[1 + d] * u[d]; }
-    const double p = gm1 * (U[D + 1] - 0.5 * ke);
-    const double Ep = U[D + 1] + p;
+    const T p = gm1 * (U[D + 1] - T(0.5) * ke);
+    const T Ep = U[D + 1] + p;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         F[d][0] = U[1 + d];
 #pragma unroll
-        for (int k = 0; k < D; ++k) F[d][1 + k] = U[1 + k] * u[d] + (k == d ? p : 0.0);
+        for (int k = 0; k < D; ++k) F[d][1 + k] = U[1 + k] * u[d] + (k == d ? p : T(0));
         F[d][D + 1] = Ep * u[d];
     }
-    return rho > 0.0 && p > 0.0 && isfinite(rho) && isfinite(p);
+    return rho > T(0) && p > T(0) && isfinite(rho) && isfinite(p);
 }
 
 // Flux of one axis.
-template <int D>
-__device__ __forceinline__ void flux_dir(const double* U, double gm1, int dir, double* F, double& p, double& un)
+template <int D, typename T = double>
+__device__ __forceinline__ void flux_dir(const T* U, T gm1, int dir, T* F, T& p, T& un)
 {
-    const double ir = 1.0 / U[0];
-    double ke = 0.0;
+    const T ir = T(1) / U[0];
+    T ke = T(0);
 #pragma unroll
     for (int d = 0; d < D; ++d) ke += U[1 + d] * U[1 + d];
-    p = gm1 * (U[D + 1] - 0.5 * ke * ir);
+    p = gm1 * (U[D + 1] - T(0.5) * ke * ir);
     un = U[1 + dir] * ir;
     F[0] = U[1 + dir];
 #pragma unroll
-    for (int k = 0; k < D; ++k) F[1 + k] = U[1 + k] * un + (k == dir ? p : 0.0);
+    for (int k = 0; k < D; ++k) F[1 + k] = U[1 + k] * un + (k == dir ? p : T(0));
     F[D + 1] = (U[D + 1] + p) * un;
 }
 
@@ -75,75 +78,74 @@ __device__ __forceinline__ void flux_dir(const double* U, double gm1, int dir, d
 // HLLC follows Toro, Spruce and Speares with Einfeldt wave-speed bounds built
 // from Roe averages; branch ties resolved as S_L >= 0 -> left, S* >= 0 -> left
 // star, S_R > 0 -> right star, else right.
-template <int D>
-__device__ __forceinline__ void riemann(const double* UL, const double* UR, int dir, int solver,
-                                        double gamma, double* F)
+template <int D, typename T = double>
+__device__ __forceinline__ void riemann(const T* UL, const T* UR, int dir, int solver, T gamma, T* F)
 {
     constexpr int NV = D + 2;
-    const double gm1 = gamma - 1.0;
-    double FL[NV], FR[NV], pL, pR, uL, uR;
-    flux_dir<D>(UL, gm1, dir, FL, pL, uL);
-    flux_dir<D>(UR, gm1, dir, FR, pR, uR);
-    const double rL = UL[0], rR = UR[0];
-    const double cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+    const T gm1 = gamma - T(1);
+    T FL[NV], FR[NV], pL, pR, uL, uR;
+    flux_dir<D, T>(UL, gm1, dir, FL, pL, uL);
+    flux_dir<D, T>(UR, gm1, dir, FR, pR, uR);
+    const T rL = UL[0], rR = UR[0];
+    const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
     if (solver == 2) {
-        const double s = fmax(fabs(uL) + cL, fabs(uR) + cR);
+        const T s = fmax(fabs(uL) + cL, fabs(uR) + cR);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * s * (UR[v] - UL[v]);
+        for (int v = 0; v < NV; ++v) F[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * s * (UR[v] - UL[v]);
         return;
     }
-    const double sL = sqrt(rL), sR = sqrt(rR);
-    const double isum = 1.0 / (sL + sR);
-    const double HL = (UL[NV - 1] + pL) / rL, HR = (UR[NV - 1] + pR) / rR;
-    double q2 = 0.0, utn = 0.0;
+    const T sL = sqrt(rL), sR = sqrt(rR);
+    const T isum = T(1) / (sL + sR);
+    const T HL = (UL[NV - 1] + pL) / rL, HR = (UR[NV - 1] + pR) / rR;
+    T q2 = T(0), utn = T(0);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const double ut = (UL[1 + d] / sL + UR[1 + d] / sR) * isum;
+        const T ut = (UL[1 + d] / sL + UR[1 + d] / sR) * isum;
         q2 += ut * ut;
         if (d == dir) utn = ut;
     }
-    const double Ht = (sL * HL + sR * HR) * isum;
-    const double ct = sqrt(gm1 * (Ht - 0.5 * q2));
-    const double SL = fmin(uL - cL, utn - ct);
-    const double SR = fmax(uR + cR, utn + ct);
+    const T Ht = (sL * HL + sR * HR) * isum;
+    const T ct = sqrt(gm1 * (Ht - T(0.5) * q2));
+    const T SL = fmin(uL - cL, utn - ct);
+    const T SR = fmax(uR + cR, utn + ct);
     if (solver == 1) {
-        if (SL >= 0.0) {
+        if (SL >= T(0)) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] = FL[v];
-        } else if (SR <= 0.0) {
+        } else if (SR <= T(0)) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] = FR[v];
         } else {
-            const double id = 1.0 / (SR - SL);
+            const T id = T(1) / (SR - SL);
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) * id;
         }
         return;
     }
-    const double mL = rL * (SL - uL), mR = rR * (SR - uR);
-    const double Ss = (pR - pL + mL * uL - mR * uR) / (mL - mR);
-    if (SL >= 0.0) {
+    const T mL = rL * (SL - uL), mR = rR * (SR - uR);
+    const T Ss = (pR - pL + mL * uL - mR * uR) / (mL - mR);
+    if (SL >= T(0)) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) F[v] = FL[v];
         return;
     }
-    if (SR <= 0.0 && !(Ss >= 0.0)) {
+    if (SR <= T(0) && !(Ss >= T(0))) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) F[v] = FR[v];
         return;
     }
     // star state on the side the contact leaves behind
-    const bool left = Ss >= 0.0;
-    const double* Uk = left ? UL : UR;
-    const double* Fk = left ? FL : FR;
-    const double Sk = left ? SL : SR;
-    const double rk = left ? rL : rR;
-    const double uk = left ? uL : uR;
-    const double pk = left ? pL : pR;
-    const double mk = left ? mL : mR;
-    const double f = mk / (Sk - Ss);
-    const double irk = 1.0 / rk;
-    double Us[NV];
+    const bool left = Ss >= T(0);
+    const T* Uk = left ? UL : UR;
+    const T* Fk = left ? FL : FR;
+    const T Sk = left ? SL : SR;
+    const T rk = left ? rL : rR;
+    const T uk = left ? uL : uR;
+    const T pk = left ? pL : pR;
+    const T mk = left ? mL : mR;
+    const T f = mk / (Sk - Ss);
+    const T irk = T(1) / rk;
+    T Us[NV];
     Us[0] = f;
 #pragma unroll
     for (int d = 0; d < D; ++d) Us[1 + d] = f * (d == dir ? Ss : Uk[1 + d] * irk);
@@ -196,6 +198,58 @@ __device__ __forceinline__ void weno1d(const double* v, double* c, const WenoArg
             wH = aH * is; wL = aL * is; wC = aC * is; wR = aR * is;
         }
         const double r = wH / gH;
+        c[1] = r * (h1 - gL * l1 - gC * m1 - gR * r1) + wL * l1 + wC * m1 + wR * r1;
+        c[2] = r * (h2 - gL * l2 - gC * m2 - gR * r2) + wL * l2 + wC * m2 + wR * r2;
+        c[3] = r * h3;
+    }
+}
+
+// Mixed-precision 1D WENO: the candidate coefficients are formed from FP64
+// stencil differences and rounded to FP32; the smoothness indicators, the
+// epsilon division and the nonlinear weights are FP64 (from the FP32
+// candidates); the weights are rounded to FP32 for the FP32 combination.
+template <int P>
+__device__ __forceinline__ void weno1d_mixed(const double* v, float* c, const WenoArgs& wa)
+{
+    const float l1 = (float)(0.5 * v[0] - 2.0 * v[1] + 1.5 * v[2]);
+    const float l2 = (float)(0.5 * v[0] - v[1] + 0.5 * v[2]);
+    const float m1 = (float)(0.5 * (v[3] - v[1]));
+    const float m2 = (float)(0.5 * v[1] - v[2] + 0.5 * v[3]);
+    const float r1 = (float)(-1.5 * v[2] + 2.0 * v[3] - 0.5 * v[4]);
+    const float r2 = (float)(0.5 * v[2] - v[3] + 0.5 * v[4]);
+    constexpr double k13_3 = 13.0 / 3.0;
+    auto is2 = [](float a, float b) { const double x = a, y = b; return x * x + k13_3 * y * y; };
+    if constexpr (P == 2) {
+        float wL = (float)wa.g[0], wC = (float)wa.g[1], wR = (float)wa.g[2];
+        if (!wa.linear) {
+            const double bL = wa.eps + is2(l1, l2), bC = wa.eps + is2(m1, m2), bR = wa.eps + is2(r1, r2);
+            const double aL = wa.g[0] / (bL * bL), aC = wa.g[1] / (bC * bC), aR = wa.g[2] / (bR * bR);
+            const double is = 1.0 / (aL + aC + aR);
+            wL = (float)(aL * is); wC = (float)(aC * is); wR = (float)(aR * is);
+        }
+        c[1] = wL * l1 + wC * m1 + wR * r1;
+        c[2] = wL * l2 + wC * m2 + wR * r2;
+    } else {
+        const float h1 = (float)((11.0 * (v[0] - v[4]) + 82.0 * (v[3] - v[1])) * (1.0 / 120.0));
+        const float h2 = (float)((-3.0 * (v[0] + v[4]) + 40.0 * (v[1] + v[3]) - 74.0 * v[2]) * (1.0 / 56.0));
+        const float h3 = (float)(((v[4] - v[0]) + 2.0 * (v[1] - v[3])) * (1.0 / 12.0));
+        const double gH = wa.g[0];
+        float wH = (float)wa.g[0], wL = (float)wa.g[1], wC = (float)wa.g[2], wR = (float)wa.g[3];
+        double ratio = 1.0;
+        if (!wa.linear) {
+            const double s1 = (double)h1 + 0.1 * (double)h3;
+            const double bH = wa.eps + (s1 * s1 + k13_3 * (double)h2 * h2 + (781.0 / 20.0) * (double)h3 * h3);
+            const double bL = wa.eps + is2(l1, l2), bC = wa.eps + is2(m1, m2), bR = wa.eps + is2(r1, r2);
+            const double aH = gH / (bH * bH), aL = wa.g[1] / (bL * bL), aC = wa.g[2] / (bC * bC),
+                         aR = wa.g[3] / (bR * bR);
+            const double is = 1.0 / (aH + aL + aC + aR);
+            ratio = aH * is / gH;
+            wL = (float)(aL * is); wC = (float)(aC * is); wR = (float)(aR * is);
+            wH = (float)(aH * is);
+        }
+        (void)wH;
+        const float r = (float)ratio;
+        const float gL = (float)wa.g[1], gC = (float)wa.g[2], gR = (float)wa.g[3];
         c[1] = r * (h1 - gL * l1 - gC * m1 - gR * r1) + wL * l1 + wC * m1 + wR * r1;
         c[2] = r * (h2 - gL * l2 - gC * m2 - gR * r2) + wL * l2 + wC * m2 + wR * r2;
         c[3] = r * h3;

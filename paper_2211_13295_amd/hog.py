@@ -21,6 +21,7 @@ HOST, DEVICE = 0, 1
 TAP_MODES, TAP_STMODES, TAP_FLUX_X, TAP_FLUX_Y, TAP_FLUX_Z = 1, 2, 3, 4, 5
 RIEMANN = {"hllc": 0, "hll": 1, "rusanov": 2}
 BC = {"periodic": 0, "outflow": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
 _ERRNAMES = {HOG_EINVAL: "EINVAL", HOG_ENOMEM: "ENOMEM", HOG_EDEVICE: "EDEVICE",
              HOG_ENONPHYS: "ENONPHYS", HOG_ESTATE: "ESTATE"}
 
@@ -85,7 +86,7 @@ def _check(rc):
 
 def make_config(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("periodic",) * 3,
                 linear_weno=False, debug=False, weno_eps=0.0, g3=(0, 0, 0), g4=(0, 0, 0, 0),
-                positivity=True):
+                positivity=True, precision="fp64"):
     c = HogConfig()
     c.ndim = ndim
     c.nx, c.ny = int(n[0]), int(n[1])
@@ -94,7 +95,7 @@ def make_config(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("peri
     c.riemann = RIEMANN[riemann] if isinstance(riemann, str) else int(riemann)
     for d in range(3):
         c.bc[d] = BC[bc[d]] if isinstance(bc[d], str) else int(bc[d])
-    c.precision = 0
+    c.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     c.linear_weno = int(bool(linear_weno))
     c.debug = int(bool(debug))
     c.positivity = int(bool(positivity))
