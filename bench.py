@@ -129,13 +129,18 @@ def cpu_baseline(order, seconds):
                       f"({el:.1f} s, OpenMP threads={threads})"}
 
 
-def mixed_run(hog, torch, pb, order, steps, ref):
+GATE_FILE = os.path.join(ROOT, "paper_2211_13295_amd", "gate_o4_3d.npz")
+
+
+def mixed_run(hog, torch, pb, order, steps, ref, gate=None):
     """Same workload on the mixed path (FP32 reconstruction / predictor / face
     states / Riemann solver, FP64 weights, face sum, update and CFL), timed the
     same way; L1 against the FP64 path's state after the same steps (that path
     matches the FP64 CPU oracle to 1e-12 relative L1 in the parity tests)."""
     import numpy as np
     g = hog.Grid.from_problem(pb, order, precision="mixed")
+    if gate is not None:
+        g.set_gate(gate[0], theta=gate[1])
     g.advance(2)
     g.set_state(pb.U)
     torch.cuda.synchronize()
@@ -146,9 +151,14 @@ def mixed_run(hog, torch, pb, order, steps, ref):
     U = g.get_state()
     rel = float(np.abs(U - ref).sum() / np.abs(ref).sum())
     rho_l1 = float(np.abs(U[0] - ref[0]).mean())
+    out = {"value": pb.U[0].size * steps / el, "unit": UNIT, "ms_per_step": el * 1e3 / steps,
+           "dtype": "f32+f64", "rel_l1_vs_fp64": rel, "density_l1_vs_fp64": rho_l1}
+    if gate is not None:
+        _, flags = g.gate_eval()
+        out["gate_theta"] = gate[1]
+        out["gated_fraction_final_state"] = float(flags.mean())
     g.close()
-    return {"value": pb.U[0].size * steps / el, "unit": UNIT, "ms_per_step": el * 1e3 / steps,
-            "dtype": "f32+f64", "rel_l1_vs_fp64": rel, "density_l1_vs_fp64": rho_l1}
+    return out
 
 
 def main():
@@ -233,7 +243,13 @@ def main():
         "predictor_fraction_of_step": prof["predictor"][0] / args.steps / step_sum if step_sum > 0 else None,
     }
     if not args.no_mixed:
-        out["mixed"] = mixed_run(hog, torch, pb, order, args.steps, g.get_state())
+        ref = g.get_state()
+        out["mixed"] = mixed_run(hog, torch, pb, order, args.steps, ref)
+        if os.path.exists(GATE_FILE):
+            import numpy as np
+            z = np.load(GATE_FILE)
+            out["mixed_gated"] = mixed_run(hog, torch, pb, order, args.steps, ref,
+                                           gate=(z["params"], float(z["theta"])))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(order, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -172,6 +172,66 @@ int hog_profile_read(hog_grid* g, double* ms, int* launches, int nstages);
  * Errors: HOG_EINVAL, HOG_EDEVICE. */
 int hog_stats(hog_grid* g, double* t, double* dt, long long* fallback_zones);
 
+/* ---------------------------------------------------------------------
+ * Learned smooth-zone gate (not in the paper; a cheaper reconstruction in
+ * zones a small network predicts to be smooth).  Network: features x ->
+ * h1 = relu(W1 x + b1) (64) -> h2 = relu(W2 h1 + b2) (64) -> logit =
+ * w3 . h2 + b3, with W1, W2, w3 and every layer input rounded to BF16, FP32
+ * biases and accumulation.  Features of a zone, per variable: the cross of
+ * the zone and its two neighbours on each side along each axis (13 zones in
+ * 3D, 9 in 2D) minus the zone value, divided by (max - min + 1e-12 max(1,
+ * |zone value|)) over the cross; order [variable][centre, x-2, x-1, x+1,
+ * x+2, y-2, ..., z+2]: nf = 65 (3D) or 36 (2D).  Parameter vector (FP32):
+ * W1[64][nf], b1[64], W2[64][64], b2[64], w3[64], b3 (row-major).
+ * --------------------------------------------------------------------- */
+
+/* Number of FP32 parameters of the gate for ndim (8449 in 3D, 6593 in 2D). */
+int hog_gate_param_count(int ndim, int* count);
+
+/* Enable the gate with the given FP32 parameters (copied, rounded to BF16 on
+ * the host) and probability threshold theta in (0,1): in every later step,
+ * the 1D WENO applications centred at an interior zone whose output
+ * probability is >= theta use the linear weights (no smoothness indicators);
+ * applications centred outside the interior keep the nonlinear weights.
+ * params = NULL disables the gate.  Synchronises.  Errors: HOG_EINVAL. */
+int hog_set_gate(hog_grid* g, const float* params, double theta);
+
+/* Evaluate the gate on the current state: host arrays of nx*ny*nz logits
+ * and/or flags (either may be NULL).  Synchronises.
+ * Errors: HOG_ESTATE (no gate or no state), HOG_EDEVICE. */
+int hog_gate_eval(hog_grid* g, float* logits, unsigned char* flags);
+
+/* Training samples from the current state (FP64 path only): for the n
+ * interior zone indices in zones (device array, x fastest) write the features
+ * feature-major to features (device, nf*n floats, [feature][sample]) and, to
+ * maxdev (device, n floats), the largest |omega_k/gamma_k - 1| of the
+ * nonlinear WENO weights over the variables and the 1D applications centred
+ * at the zone (a zone is labelled smooth when it is <= 0.25).  Stream-ordered,
+ * no synchronisation.  Errors: HOG_EINVAL, HOG_ESTATE. */
+int hog_harvest(hog_grid* g, const long long* zones, long long n, float* features, float* maxdev);
+
+/* Training of the gate network on the GPU (FP32 masters, Adam, BF16-rounded
+ * operands in the forward pass as in inference; gradients summed over the
+ * batch in a fixed order).  The caller owns a device workspace of
+ * hog_mlp_workspace_size() bytes and the batch arrays: X (device, n*nf
+ * floats, sample-major), y (device, n labels 0/1), w (device, n per-sample
+ * loss weights, or NULL for 1).  Loss: weighted binary cross entropy, mean
+ * over the batch. */
+typedef struct hog_mlp hog_mlp;
+int hog_mlp_workspace_size(int nf, int batch_max, size_t* bytes);
+int hog_mlp_create(int nf, int batch_max, void* workspace, size_t bytes, void* hip_stream, hog_mlp** out);
+int hog_mlp_destroy(hog_mlp* m);
+/* Copy the FP32 parameter vector in (resets the Adam moments) / out. */
+int hog_mlp_set_params(hog_mlp* m, const float* params);
+int hog_mlp_get_params(hog_mlp* m, float* params);
+/* Loss and gradient (host outputs, either may be NULL), no update; synchronises. */
+int hog_mlp_grads(hog_mlp* m, const float* X, const float* y, const float* w, int n, float* grads, float* loss);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with learning rate lr; *loss
+ * (host, may be NULL: then no synchronisation) receives the pre-step loss. */
+int hog_mlp_step(hog_mlp* m, const float* X, const float* y, const float* w, int n, float lr, float* loss);
+/* Logits of n samples (device output). */
+int hog_mlp_predict(hog_mlp* m, const float* X, int n, float* logits);
+
 /* Zone index (x fastest) of the first non-physical zone found by the last
  * check, or -1. */
 long long hog_last_bad_zone(hog_grid* g);

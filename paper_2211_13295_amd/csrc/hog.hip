@@ -12,6 +12,7 @@
 
 #include "hog.h"
 #include "hog_kernels.h"
+#include "hog_gate.h"
 
 using namespace hog;
 
@@ -46,7 +47,8 @@ struct Plan {
     Box I, AX, BY, R, FB[3];
     int ms, mst;
     // byte offsets in the workspace
-    size_t off_info, off_U[2], off_A, off_B, off_W, off_FP, off_F[3], off_Q, off_stage, total;
+    size_t off_info, off_U[2], off_A, off_B, off_W, off_FP, off_F[3], off_Q, off_stage;
+    size_t off_gate, off_flags, off_logits, total;
 };
 
 int nmodes(int d, int p) { int r = 1; for (int i = 1; i <= d; ++i) r = r * (p + i) / i; return r; }
@@ -134,6 +136,9 @@ void plan(const hog_config* c, Plan* P)
     for (int d = 0; d < 3; ++d) P->off_F[d] = (d < nd) ? take(sizeof(double) * nv * box_size(P->FB[d])) : 0;
     P->off_Q = c->debug ? take(sizeof(double) * P->mst * nv * box_size(P->R)) : 0;
     P->off_stage = take(sizeof(double) * nv * box_size(P->I));
+    P->off_gate = take(nd == 3 ? sizeof(GateParams<3>) : sizeof(GateParams<2>));
+    P->off_flags = take(box_size(P->I));
+    P->off_logits = take(sizeof(float) * box_size(P->I));
     P->total = o;
 }
 
@@ -154,6 +159,11 @@ struct hog_grid {
     double* U[2];
     void *A, *B, *W, *FP, *Q;     // element type: double (FP64) or float (mixed)
     double *F[3], *stage;
+    // learned gate (device copy of the parameters, per-zone flags and logits)
+    bool gate_on;
+    void* gate;
+    unsigned char* flags;
+    float* logits;
     // stage timing: pairs of events per recorded stage launch, evaluated on read
     bool profiling;
     std::vector<hipEvent_t> ev_pool;
@@ -226,10 +236,16 @@ int enqueue_step_t(hog_grid* g, double dt_user)
     }
     {
         StageMark m(g, 1);
-        k_recon_x<D, P, T><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa);
-        k_recon_y<D, P, T><<<nblocks(box_size(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa);
+        const unsigned char* gf = nullptr;
+        if (g->gate_on) {
+            k_gate_infer<D><<<nblocks(box_size(L.I), 16), 64, 0, s>>>(
+                Uc, L.pad, L.I, static_cast<const GateParams<D>*>(g->gate), g->flags, nullptr);
+            gf = g->flags;
+        }
+        k_recon_x<D, P, T><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa, gf, L.I);
+        k_recon_y<D, P, T><<<nblocks(box_size(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa, gf, L.I);
         if constexpr (D == 3)
-            k_recon_z<P, T><<<nblocks(box_size(L.R), 256), 256, 0, s>>>(B, L.BY, L.R, W, g->wa);
+            k_recon_z<P, T><<<nblocks(box_size(L.R), 256), 256, 0, s>>>(B, L.BY, L.R, W, g->wa, gf, L.I);
     }
     {
         StageMark m(g, 2);
@@ -369,6 +385,10 @@ int hog_create(const hog_config* cfg, void* workspace, size_t bytes, void* hip_s
     for (int d = 0; d < 3; ++d) g->F[d] = (d < P.nd) ? reinterpret_cast<double*>(g->ws + P.off_F[d]) : nullptr;
     g->Q = cfg->debug ? static_cast<void*>(g->ws + P.off_Q) : nullptr;
     g->stage = reinterpret_cast<double*>(g->ws + P.off_stage);
+    g->gate_on = false;
+    g->gate = g->ws + P.off_gate;
+    g->flags = reinterpret_cast<unsigned char*>(g->ws + P.off_flags);
+    g->logits = reinterpret_cast<float*>(g->ws + P.off_logits);
     k_reset<<<1, 1, 0, g->stream>>>(g->info, 0.0, 1);
     rc = launch_check("reset");
     if (rc) { delete g; return rc; }
@@ -622,6 +642,274 @@ int hog_debug_tap(hog_grid* g, int tap, void* dst, size_t bytes)
         return HOG_OK;
     }
     return fail(HOG_EINVAL, "unknown tap %d", tap);
+}
+
+// ------------------------------------------------------------------------
+// Learned gate
+// ------------------------------------------------------------------------
+static uint16_t host_bf16(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+int hog_gate_param_count(int ndim, int* count)
+{
+    if ((ndim != 2 && ndim != 3) || !count) return fail(HOG_EINVAL, "bad arguments");
+    *count = (ndim == 3) ? GateShape<3>::NPARAM : GateShape<2>::NPARAM;
+    return HOG_OK;
+}
+
+extern "C++" {
+template <int D>
+static int set_gate_t(hog_grid* g, const float* prm, double theta)
+{
+    using G = GateShape<D>;
+    using O = MlpOffsets<G::NF>;
+    GateParams<D> h;
+    std::memset(&h, 0, sizeof h);
+    for (int o = 0; o < kHidden; ++o)
+        for (int f = 0; f < G::NF; ++f) h.W1[o][f] = host_bf16(prm[O::W1 + o * G::NF + f]);
+    for (int o = 0; o < kHidden; ++o) {
+        h.b1[o] = prm[O::B1 + o];
+        h.b2[o] = prm[O::B2 + o];
+        h.w3[o] = host_bf16(prm[O::W3 + o]);
+        for (int q = 0; q < kHidden; ++q) h.W2[o][q] = host_bf16(prm[O::W2 + o * kHidden + q]);
+    }
+    h.b3 = prm[O::B3];
+    h.logit_thr = (float)std::log(theta / (1.0 - theta));
+    HIP_TRY(hipMemcpyAsync(g->gate, &h, sizeof h, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return HOG_OK;
+}
+} // extern "C++"
+
+int hog_set_gate(hog_grid* g, const float* params, double theta)
+{
+    if (!g) return fail(HOG_EINVAL, "NULL handle");
+    if (!params) { g->gate_on = false; return HOG_OK; }
+    if (!(theta > 0.0 && theta < 1.0)) return fail(HOG_EINVAL, "theta must be in (0, 1)");
+    const int rc = (g->P.nd == 3) ? set_gate_t<3>(g, params, theta) : set_gate_t<2>(g, params, theta);
+    if (rc) return rc;
+    g->gate_on = true;
+    return HOG_OK;
+}
+
+static void enqueue_ghost(hog_grid* g)
+{
+    const Plan& L = g->P;
+    const long long npad = (long long)L.pad.np[0] * L.pad.np[1] * L.pad.np[2];
+    if (L.nd == 3)
+        k_ghost<3><<<nblocks(npad, 256), 256, 0, g->stream>>>(g->U[g->cur], L.pad, L.n[0], L.n[1], L.n[2],
+                                                               g->cfg.bc[0], g->cfg.bc[1], g->cfg.bc[2]);
+    else
+        k_ghost<2><<<nblocks(npad, 256), 256, 0, g->stream>>>(g->U[g->cur], L.pad, L.n[0], L.n[1], L.n[2],
+                                                               g->cfg.bc[0], g->cfg.bc[1], g->cfg.bc[2]);
+}
+
+int hog_gate_eval(hog_grid* g, float* logits, unsigned char* flags)
+{
+    if (!g) return fail(HOG_EINVAL, "NULL handle");
+    if (!g->gate_on) return fail(HOG_ESTATE, "no gate set");
+    if (!g->have_state) return fail(HOG_ESTATE, "no state set");
+    const Plan& L = g->P;
+    const long long N = box_size(L.I);
+    enqueue_ghost(g);
+    if (L.nd == 3)
+        k_gate_infer<3><<<nblocks(N, 16), 64, 0, g->stream>>>(g->U[g->cur], L.pad, L.I,
+                                                               static_cast<const GateParams<3>*>(g->gate), g->flags,
+                                                               g->logits);
+    else
+        k_gate_infer<2><<<nblocks(N, 16), 64, 0, g->stream>>>(g->U[g->cur], L.pad, L.I,
+                                                               static_cast<const GateParams<2>*>(g->gate), g->flags,
+                                                               g->logits);
+    int rc = launch_check("gate");
+    if (rc) return rc;
+    if (logits) HIP_TRY(hipMemcpyAsync(logits, g->logits, sizeof(float) * N, hipMemcpyDeviceToHost, g->stream));
+    if (flags) HIP_TRY(hipMemcpyAsync(flags, g->flags, N, hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return HOG_OK;
+}
+
+extern "C++" {
+template <int D, int P>
+static void enqueue_harvest(hog_grid* g, const long long* zones, long long n, float* feat, float* maxdev)
+{
+    const Plan& L = g->P;
+    hipStream_t s = g->stream;
+    double* Uc = g->U[g->cur];
+    double* A = static_cast<double*>(g->A);
+    double* B = static_cast<double*>(g->B);
+    k_recon_x<D, P, double><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa, nullptr, L.I);
+    k_recon_y<D, P, double><<<nblocks(box_size(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa, nullptr, L.I);
+    k_harvest<D, P><<<nblocks(n, 256), 256, 0, s>>>(Uc, L.pad, L.I, A, L.AX, B, L.BY, zones, n, g->wa, feat, maxdev);
+}
+} // extern "C++"
+
+int hog_harvest(hog_grid* g, const long long* zones, long long n, float* features, float* maxdev)
+{
+    if (!g || !zones || !features || !maxdev || n < 0) return fail(HOG_EINVAL, "bad arguments");
+    if (!g->have_state) return fail(HOG_ESTATE, "no state set");
+    if (g->cfg.precision != HOG_FP64) return fail(HOG_EINVAL, "harvest runs on the FP64 path");
+    if (n == 0) return HOG_OK;
+    enqueue_ghost(g);
+    switch (g->P.nd * 10 + g->P.p) {
+    case 22: enqueue_harvest<2, 2>(g, zones, n, features, maxdev); break;
+    case 23: enqueue_harvest<2, 3>(g, zones, n, features, maxdev); break;
+    case 32: enqueue_harvest<3, 2>(g, zones, n, features, maxdev); break;
+    case 33: enqueue_harvest<3, 3>(g, zones, n, features, maxdev); break;
+    }
+    return launch_check("harvest");
+}
+
+} // extern "C"
+
+// ------------------------------------------------------------------------
+// Gate training
+// ------------------------------------------------------------------------
+struct hog_mlp {
+    int nf, batch_max, np, t;
+    hipStream_t stream;
+    float *prm, *m, *v, *grad, *xb, *h1, *h2, *d1, *d2, *dz, *loss, *logit, *lsum;
+};
+
+static size_t mlp_floats(int nf, int batch_max, int np)
+{
+    return 4 * (size_t)np + (size_t)batch_max * (nf + 4 * kHidden + 3) + 64;
+}
+
+static int mlp_nparam(int nf) { return kHidden * nf + kHidden + kHidden * kHidden + kHidden + kHidden + 1; }
+
+extern "C" {
+
+int hog_mlp_workspace_size(int nf, int batch_max, size_t* bytes)
+{
+    if ((nf != 36 && nf != 65) || batch_max < 1 || !bytes) return fail(HOG_EINVAL, "nf must be 36 or 65");
+    *bytes = sizeof(float) * mlp_floats(nf, batch_max, mlp_nparam(nf));
+    return HOG_OK;
+}
+
+int hog_mlp_create(int nf, int batch_max, void* ws, size_t bytes, void* stream, hog_mlp** out)
+{
+    size_t need = 0;
+    int rc = hog_mlp_workspace_size(nf, batch_max, &need);
+    if (rc) return rc;
+    if (!ws || !out) return fail(HOG_EINVAL, "NULL argument");
+    if (bytes < need) return fail(HOG_ENOMEM, "workspace too small: %zu < %zu", bytes, need);
+    hog_mlp* m = new (std::nothrow) hog_mlp();
+    if (!m) return fail(HOG_ENOMEM, "host allocation failed");
+    m->nf = nf; m->batch_max = batch_max; m->np = mlp_nparam(nf); m->t = 0;
+    m->stream = static_cast<hipStream_t>(stream);
+    float* f = static_cast<float*>(ws);
+    m->prm = f; f += m->np;
+    m->m = f; f += m->np;
+    m->v = f; f += m->np;
+    m->grad = f; f += m->np;
+    m->xb = f; f += (size_t)batch_max * nf;
+    m->h1 = f; f += (size_t)batch_max * kHidden;
+    m->h2 = f; f += (size_t)batch_max * kHidden;
+    m->d1 = f; f += (size_t)batch_max * kHidden;
+    m->d2 = f; f += (size_t)batch_max * kHidden;
+    m->dz = f; f += batch_max;
+    m->loss = f; f += batch_max;
+    m->logit = f; f += batch_max;
+    m->lsum = f;
+    HIP_TRY(hipMemsetAsync(ws, 0, need, m->stream));
+    *out = m;
+    return HOG_OK;
+}
+
+int hog_mlp_destroy(hog_mlp* m)
+{
+    delete m;
+    return HOG_OK;
+}
+
+int hog_mlp_set_params(hog_mlp* m, const float* params)
+{
+    if (!m || !params) return fail(HOG_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(m->prm, params, sizeof(float) * m->np, hipMemcpyHostToDevice, m->stream));
+    HIP_TRY(hipMemsetAsync(m->m, 0, sizeof(float) * m->np, m->stream));
+    HIP_TRY(hipMemsetAsync(m->v, 0, sizeof(float) * m->np, m->stream));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    m->t = 0;
+    return HOG_OK;
+}
+
+int hog_mlp_get_params(hog_mlp* m, float* params)
+{
+    if (!m || !params) return fail(HOG_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(params, m->prm, sizeof(float) * m->np, hipMemcpyDeviceToHost, m->stream));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    return HOG_OK;
+}
+
+static int mlp_backward(hog_mlp* m, const float* X, const float* y, const float* w, int n)
+{
+    if (n < 1 || n > m->batch_max || !X || !y) return fail(HOG_EINVAL, "batch must be 1..%d", m->batch_max);
+    if (m->nf == 65) {
+        k_mlp_fwd_bwd<65><<<nblocks(n, 128), 128, 0, m->stream>>>(X, y, w, n, m->prm, m->xb, m->h1, m->h2, m->d1,
+                                                                  m->d2, m->dz, m->loss, m->logit);
+        k_mlp_wgrad<65><<<nblocks(m->np, 256), 256, 0, m->stream>>>(m->xb, m->h1, m->h2, m->d1, m->d2, m->dz, n,
+                                                                    m->grad);
+    } else {
+        k_mlp_fwd_bwd<36><<<nblocks(n, 128), 128, 0, m->stream>>>(X, y, w, n, m->prm, m->xb, m->h1, m->h2, m->d1,
+                                                                  m->d2, m->dz, m->loss, m->logit);
+        k_mlp_wgrad<36><<<nblocks(m->np, 256), 256, 0, m->stream>>>(m->xb, m->h1, m->h2, m->d1, m->d2, m->dz, n,
+                                                                    m->grad);
+    }
+    k_sum_fixed<<<1, 256, 0, m->stream>>>(m->loss, n, m->lsum);
+    return launch_check("mlp backward");
+}
+
+int hog_mlp_grads(hog_mlp* m, const float* X, const float* y, const float* w, int n, float* grads, float* loss)
+{
+    if (!m) return fail(HOG_EINVAL, "NULL handle");
+    int rc = mlp_backward(m, X, y, w, n);
+    if (rc) return rc;
+    if (grads) HIP_TRY(hipMemcpyAsync(grads, m->grad, sizeof(float) * m->np, hipMemcpyDeviceToHost, m->stream));
+    if (loss) HIP_TRY(hipMemcpyAsync(loss, m->lsum, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+    HIP_TRY(hipStreamSynchronize(m->stream));
+    return HOG_OK;
+}
+
+int hog_mlp_step(hog_mlp* m, const float* X, const float* y, const float* w, int n, float lr, float* loss)
+{
+    if (!m) return fail(HOG_EINVAL, "NULL handle");
+    if (!(lr > 0.0f)) return fail(HOG_EINVAL, "lr must be > 0");
+    int rc = mlp_backward(m, X, y, w, n);
+    if (rc) return rc;
+    m->t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)m->t), c2 = 1.0f - std::pow(b2, (float)m->t);
+    k_mlp_adam<<<nblocks(m->np, 256), 256, 0, m->stream>>>(m->prm, m->m, m->v, m->grad, m->np, lr, b1, b2, 1e-8f,
+                                                            c1, c2);
+    rc = launch_check("adam");
+    if (rc) return rc;
+    if (loss) {
+        HIP_TRY(hipMemcpyAsync(loss, m->lsum, sizeof(float), hipMemcpyDeviceToHost, m->stream));
+        HIP_TRY(hipStreamSynchronize(m->stream));
+    }
+    return HOG_OK;
+}
+
+int hog_mlp_predict(hog_mlp* m, const float* X, int n, float* logits)
+{
+    if (!m || !X || !logits || n < 1) return fail(HOG_EINVAL, "bad arguments");
+    for (int s0 = 0; s0 < n; s0 += m->batch_max) {
+        const int b = (n - s0 < m->batch_max) ? n - s0 : m->batch_max;
+        if (m->nf == 65)
+            k_mlp_fwd_bwd<65><<<nblocks(b, 128), 128, 0, m->stream>>>(X + (size_t)s0 * 65, nullptr, nullptr, b, m->prm,
+                                                                      nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                                      nullptr, nullptr, logits + s0);
+        else
+            k_mlp_fwd_bwd<36><<<nblocks(b, 128), 128, 0, m->stream>>>(X + (size_t)s0 * 36, nullptr, nullptr, b, m->prm,
+                                                                      nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                                      nullptr, nullptr, logits + s0);
+    }
+    return launch_check("mlp predict");
 }
 
 } // extern "C"

@@ -188,9 +188,22 @@ __device__ __forceinline__ void weno_line(const double* line, T* c, const WenoAr
     else weno1d_mixed<P>(line, c, wa);
 }
 
+// Weights for the 1D applications centred at zone (i,j,k): linear when the
+// learned gate marked that interior zone smooth.
+__device__ __forceinline__ WenoArgs gated(const WenoArgs& wa, const unsigned char* __restrict__ gate, const Box& I,
+                                          int i, int j, int k)
+{
+    WenoArgs w = wa;
+    if (gate && i >= 0 && i < I.n[0] && j >= 0 && j < I.n[1] && k >= 0 && k < I.n[2] &&
+        gate[((long long)k * I.n[1] + j) * I.n[0] + i])
+        w.linear = 1;
+    return w;
+}
+
 template <int D, int P, typename T>
 __global__ __launch_bounds__(256) void k_recon_x(const double* __restrict__ U, Pad p, Box AX,
-                                                 T* __restrict__ A, WenoArgs wa)
+                                                 T* __restrict__ A, WenoArgs wa0,
+                                                 const unsigned char* __restrict__ gate, Box I)
 {
     constexpr int NV = D + 2;
     const long long nA = box_size(AX);
@@ -198,6 +211,7 @@ __global__ __launch_bounds__(256) void k_recon_x(const double* __restrict__ U, P
     if (z >= nA) return;
     int i, j, k;
     box_ijk(AX, z, i, j, k);
+    const WenoArgs wa = gated(wa0, gate, I, i, j, k);
     const long long base = pad_index(p, i, j, k);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -214,7 +228,8 @@ __global__ __launch_bounds__(256) void k_recon_x(const double* __restrict__ U, P
 
 template <int D, int P, typename T>
 __global__ __launch_bounds__(256) void k_recon_y(const T* __restrict__ A, Box AX, Box BY,
-                                                 T* __restrict__ B, WenoArgs wa)
+                                                 T* __restrict__ B, WenoArgs wa0,
+                                                 const unsigned char* __restrict__ gate, Box I)
 {
     constexpr int NV = D + 2;
     constexpr Pairs<P> PR{};
@@ -223,6 +238,7 @@ __global__ __launch_bounds__(256) void k_recon_y(const T* __restrict__ A, Box AX
     if (z >= nB) return;
     int i, j, k;
     box_ijk(BY, z, i, j, k);
+    const WenoArgs wa = gated(wa0, gate, I, i, j, k);
     const long long c0 = box_index(AX, i, j, k);
     const long long sy = AX.n[0];
 #pragma unroll
@@ -244,7 +260,8 @@ __global__ __launch_bounds__(256) void k_recon_y(const T* __restrict__ A, Box AX
 
 template <int P, typename T>
 __global__ __launch_bounds__(256) void k_recon_z(const T* __restrict__ B, Box BY, Box R,
-                                                 T* __restrict__ W, WenoArgs wa)
+                                                 T* __restrict__ W, WenoArgs wa0,
+                                                 const unsigned char* __restrict__ gate, Box I)
 {
     constexpr int NV = 5;
     constexpr Modes<3, P> M{};
@@ -254,6 +271,7 @@ __global__ __launch_bounds__(256) void k_recon_z(const T* __restrict__ B, Box BY
     if (z >= nR) return;
     int i, j, k;
     box_ijk(R, z, i, j, k);
+    const WenoArgs wa = gated(wa0, gate, I, i, j, k);
     const long long c0 = box_index(BY, i, j, k);
     const long long sz = (long long)BY.n[0] * BY.n[1];
 #pragma unroll

@@ -1,0 +1,140 @@
+"""Train the learned smooth-zone gate on the GPU.
+
+Data: training samples harvested by the library (hog_harvest) from FP64
+fourth-order runs of the 3D workloads -- the extruded vortex with seeded
+density modes (periodic) and the multi-blast (outflow) -- at several steps of
+each run; label smooth <=> the largest |omega_k/gamma_k - 1| over the
+variables and the 1D applications centred at the zone is <= 0.25.  The set is
+stratified to equal class counts, split 90/10 (seeded), and the network is
+trained with the library's kernels (hog_mlp_step: Adam, batch 4096).  The
+probability threshold is the smallest one whose false-smooth rate on the
+held-out 10% (non-smooth zones predicted smooth / non-smooth zones) is at
+most the target.
+
+    python -m paper_2211_13295_amd.gate_train --out paper_2211_13295_amd/gate_o4_3d.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def he_init(nf, seed):
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((64, nf)) * np.sqrt(2.0 / nf)
+    W2 = rng.standard_normal((64, 64)) * np.sqrt(2.0 / 64)
+    w3 = rng.standard_normal(64) * np.sqrt(1.0 / 64)
+    return np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), w3, np.zeros(1)]).astype(np.float32)
+
+
+def harvest(hog, torch, problems, order, steps_between, snapshots, per_snapshot, seed, log):
+    rng = np.random.default_rng(seed)
+    feats, devs = [], []
+    for pb in problems:
+        g = hog.Grid.from_problem(pb, order)
+        N = pb.U[0].size
+        for s in range(snapshots):
+            zones = np.arange(N) if per_snapshot >= N else np.sort(rng.choice(N, per_snapshot, replace=False))
+            F, d = g.harvest(zones)
+            feats.append(F)
+            devs.append(d)
+            log(f"  harvest {pb.meta.get('name')} n={pb.n[0]} snapshot {s}: {len(zones)} zones, "
+                f"smooth fraction {float((d <= 0.25).float().mean()):.3f}")
+            if s + 1 < snapshots:
+                g.advance(steps_between)
+        g.close()
+        torch.cuda.empty_cache()
+    return torch.cat(feats), torch.cat(devs)
+
+
+def train(hog, torch, X, y, epochs, lr, batch, seed, log):
+    m = hog.Mlp(X.shape[1], batch_max=batch)
+    m.set_params(he_init(X.shape[1], seed))
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    n = X.shape[0]
+    steps = max(1, epochs * n // batch)
+    t0 = time.time()
+    for it in range(steps):
+        idx = torch.randint(0, n, (batch,), generator=gen).cuda()
+        want = (it % 200 == 0) or it == steps - 1
+        loss = m.step(X[idx].contiguous(), y[idx].contiguous(), None, lr=lr, want_loss=want)
+        if want:
+            log(f"  step {it}/{steps} loss {loss:.4f} ({time.time() - t0:.1f} s)")
+    return m
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--out", default=os.path.join(HERE, "gate_o4_3d.npz"))
+    ap.add_argument("--n-vortex", type=int, default=128)
+    ap.add_argument("--n-blast", type=int, default=128)
+    ap.add_argument("--snapshots", type=int, default=5)
+    ap.add_argument("--steps-between", type=int, default=10)
+    ap.add_argument("--per-snapshot", type=int, default=600000)
+    ap.add_argument("--samples", type=int, default=5000000)
+    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--target-fsr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=4)
+    a = ap.parse_args(argv)
+
+    import torch
+    import icgen
+    from paper_2211_13295_amd import hog
+
+    def log(msg):
+        print(msg, flush=True)
+
+    hog.load()
+    probs = [icgen.vortex3d_perturbed(n=a.n_vortex, seed=2), icgen.multiblast(n=a.n_blast, seed=3)]
+    log("harvesting")
+    X, dev = harvest(hog, torch, probs, 4, a.steps_between, a.snapshots, a.per_snapshot, a.seed, log)
+    y = (dev <= 0.25).float()
+    # stratify to equal class counts, seeded
+    gen = torch.Generator(device="cpu").manual_seed(a.seed)
+    pos = torch.nonzero(y > 0).flatten().cpu()
+    neg = torch.nonzero(y == 0).flatten().cpu()
+    k = min(len(pos), len(neg), a.samples // 2)
+    pos = pos[torch.randperm(len(pos), generator=gen)[:k]]
+    neg = neg[torch.randperm(len(neg), generator=gen)[:k]]
+    sel = torch.cat([pos, neg])[torch.randperm(2 * k, generator=gen)].cuda()
+    X, y = X[sel].contiguous(), y[sel].contiguous()
+    ntr = int(0.9 * X.shape[0])
+    Xtr, ytr, Xva, yva = X[:ntr], y[:ntr], X[ntr:], y[ntr:]
+    log(f"training set {ntr}, held out {X.shape[0] - ntr} (balanced)")
+    m = train(hog, torch, Xtr, ytr, a.epochs, a.lr, a.batch, a.seed, log)
+    lv = m.predict(Xva)
+    neg_l = lv[yva == 0]
+    # smallest logit threshold with false-smooth rate <= target
+    q = torch.sort(neg_l).values
+    kq = int(np.ceil((1.0 - a.target_fsr) * len(q))) - 1
+    thr = float(q[min(max(kq, 0), len(q) - 1)]) + 1e-6
+    pred = lv >= thr
+    fsr = float((pred & (yva == 0)).float().sum() / max(1, int((yva == 0).sum())))
+    recall = float((pred & (yva > 0)).float().sum() / max(1, int((yva > 0).sum())))
+    acc = float(((lv >= 0) == (yva > 0)).float().mean())
+    theta = float(1.0 / (1.0 + np.exp(-thr)))
+    params = m.get_params()
+    stats = dict(theta=theta, logit_threshold=thr, heldout_false_smooth_rate=fsr, heldout_smooth_recall=recall,
+                 heldout_accuracy_at_half=acc, train_samples=ntr, heldout_samples=int(X.shape[0] - ntr),
+                 sources=[p.meta.get("name") + f"_{p.n[0]}" for p in probs], snapshots=a.snapshots,
+                 steps_between=a.steps_between, epochs=a.epochs, lr=a.lr, batch=a.batch, seed=a.seed)
+    np.savez(a.out, params=params, theta=np.array(theta))
+    with open(os.path.splitext(a.out)[0] + ".json", "w") as f:
+        json.dump(stats, f, indent=1)
+    log(json.dumps(stats))
+
+
+if __name__ == "__main__":
+    main()

@@ -69,6 +69,23 @@ def load():
     L.hog_profile_enable.argtypes = [vp, C.c_int]
     L.hog_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_int]
     L.hog_stats.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
+    fp, ip_ = C.POINTER(C.c_float), C.POINTER(C.c_int)
+    L.hog_gate_param_count.argtypes = [C.c_int, ip_]
+    L.hog_set_gate.argtypes = [vp, vp, C.c_double]
+    L.hog_gate_eval.argtypes = [vp, vp, vp]
+    L.hog_harvest.argtypes = [vp, vp, C.c_longlong, vp, vp]
+    L.hog_mlp_workspace_size.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_size_t)]
+    L.hog_mlp_create.argtypes = [C.c_int, C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.hog_mlp_destroy.argtypes = [vp]
+    L.hog_mlp_set_params.argtypes = [vp, vp]
+    L.hog_mlp_get_params.argtypes = [vp, vp]
+    L.hog_mlp_grads.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
+    L.hog_mlp_step.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, vp]
+    L.hog_mlp_predict.argtypes = [vp, vp, C.c_int, vp]
+    for f in ("hog_gate_param_count", "hog_set_gate", "hog_gate_eval", "hog_harvest", "hog_mlp_workspace_size",
+              "hog_mlp_create", "hog_mlp_destroy", "hog_mlp_set_params", "hog_mlp_get_params", "hog_mlp_grads",
+              "hog_mlp_step", "hog_mlp_predict"):
+        getattr(L, f).restype = C.c_int
     L.hog_last_bad_zone.argtypes = [vp]
     L.hog_last_bad_zone.restype = C.c_longlong
     for f in ("hog_workspace_size", "hog_create", "hog_destroy", "hog_set_state", "hog_get_state",
@@ -229,5 +246,129 @@ class Grid:
         _check(load().hog_stats(self._h, C.byref(t), C.byref(dt), C.byref(nb)))
         return {"t": t.value, "dt": dt.value, "fallback_zones": nb.value}
 
+    # ---- learned gate
+    def set_gate(self, params, theta=0.5):
+        """params: FP32 vector (pack_params) or None to disable."""
+        if params is None:
+            _check(load().hog_set_gate(self._h, None, 0.5))
+            return
+        v = np.ascontiguousarray(params, dtype=np.float32)
+        assert v.size == param_count(self.ndim)
+        _check(load().hog_set_gate(self._h, v.ctypes.data_as(C.c_void_p), float(theta)))
+
+    def gate_eval(self):
+        n = self.nzones
+        logits = np.empty(n, np.float32)
+        flags = np.empty(n, np.uint8)
+        _check(load().hog_gate_eval(self._h, logits.ctypes.data_as(C.c_void_p), flags.ctypes.data_as(C.c_void_p)))
+        return logits.reshape(self.shape[1:]), flags.reshape(self.shape[1:])
+
+    def harvest(self, zones):
+        """Features (n, nf) and max weight deviation (n,) of interior zones (flat indices)."""
+        torch = self._torch
+        z = torch.as_tensor(np.asarray(zones, dtype=np.int64), device="cuda")
+        n = z.numel()
+        nf = (self.ndim + 2) * (4 * self.ndim + 1)
+        feat = torch.empty(nf * max(n, 1), dtype=torch.float32, device="cuda")
+        dev = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+        _check(load().hog_harvest(self._h, C.c_void_p(z.data_ptr()), n, C.c_void_p(feat.data_ptr()),
+                                  C.c_void_p(dev.data_ptr())))
+        torch.cuda.current_stream().synchronize()
+        return feat[: nf * n].view(nf, n).t().contiguous(), dev[:n]
+
     def last_bad_zone(self):
         return load().hog_last_bad_zone(self._h)
+
+
+def param_count(ndim):
+    n = C.c_int(0)
+    _check(load().hog_gate_param_count(ndim, C.byref(n)))
+    return n.value
+
+
+def pack_params(W1, b1, W2, b2, w3, b3):
+    """FP32 parameter vector of the gate network in the C ABI's order."""
+    return np.concatenate([np.asarray(a, np.float32).reshape(-1) for a in (W1, b1, W2, b2, w3, b3)])
+
+
+def unpack_params(v, nf, hidden=64):
+    v = np.asarray(v, np.float32)
+    o = 0
+    out = {}
+    for k, shp in (("W1", (hidden, nf)), ("b1", (hidden,)), ("W2", (hidden, hidden)), ("b2", (hidden,)),
+                   ("w3", (hidden,)), ("b3", (1,))):
+        size = int(np.prod(shp))
+        out[k] = v[o:o + size].reshape(shp).copy()
+        o += size
+    return out
+
+
+class Mlp:
+    """Training handle of the gate network (GPU kernels; torch only allocates)."""
+
+    def __init__(self, nf, batch_max=4096):
+        import torch
+        self._torch = torch
+        self.nf, self.batch_max = nf, batch_max
+        L = load()
+        nb = C.c_size_t(0)
+        _check(L.hog_mlp_workspace_size(nf, batch_max, C.byref(nb)))
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        _check(L.hog_mlp_create(nf, batch_max, C.c_void_p(self.workspace.data_ptr()), nb.value,
+                                C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(h)))
+        self._h = h
+        self.np = 64 * nf + 64 + 64 * 64 + 64 + 64 + 1
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hog_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, vec):
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        assert v.size == self.np
+        _check(load().hog_mlp_set_params(self._h, v.ctypes.data_as(C.c_void_p)))
+
+    def get_params(self):
+        v = np.empty(self.np, np.float32)
+        _check(load().hog_mlp_get_params(self._h, v.ctypes.data_as(C.c_void_p)))
+        return v
+
+    def _dev(self, a, dtype):
+        torch = self._torch
+        if isinstance(a, torch.Tensor):
+            return a.to(device="cuda", dtype=dtype).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+    def grads(self, X, y, w=None):
+        X, y = self._dev(X, self._torch.float32), self._dev(y, self._torch.float32)
+        w = None if w is None else self._dev(w, self._torch.float32)
+        g = np.empty(self.np, np.float32)
+        loss = np.zeros(1, np.float32)
+        _check(load().hog_mlp_grads(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(y.data_ptr()),
+                                    None if w is None else C.c_void_p(w.data_ptr()), int(y.numel()),
+                                    g.ctypes.data_as(C.c_void_p), loss.ctypes.data_as(C.c_void_p)))
+        return float(loss[0]), g
+
+    def step(self, X, y, w=None, lr=1e-3, want_loss=True):
+        loss = np.zeros(1, np.float32)
+        _check(load().hog_mlp_step(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(y.data_ptr()),
+                                   None if w is None else C.c_void_p(w.data_ptr()), int(y.numel()), float(lr),
+                                   loss.ctypes.data_as(C.c_void_p) if want_loss else None))
+        return float(loss[0]) if want_loss else None
+
+    def predict(self, X):
+        torch = self._torch
+        X = self._dev(X, torch.float32)
+        n = X.numel() // self.nf
+        out = torch.empty(n, dtype=torch.float32, device="cuda")
+        _check(load().hog_mlp_predict(self._h, C.c_void_p(X.data_ptr()), n, C.c_void_p(out.data_ptr())))
+        torch.cuda.current_stream().synchronize()
+        return out
