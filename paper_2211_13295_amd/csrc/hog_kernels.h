@@ -294,15 +294,23 @@ __global__ __launch_bounds__(256) void k_recon_z(const T* __restrict__ B, Box BY
 }
 
 // ------------------------------------------------------------------------
-// a4: ADER predictor.  One wavefront per zone group.  Node phase: lane =
-// (zone slot, spatial Gauss node); each lane keeps the time-independent part
-// of q at its node in registers, evaluates the time modes from LDS, forms the
-// physical fluxes at every time node and contracts them against the time
-// basis.  Projection phase: the contracted fluxes go to LDS as one row per
-// (zone, flux time mode, axis, variable) "slice"; one lane then owns a whole
-// slice and does its x -> y -> z sum-factorised L2 projection in registers,
-// writing the modal coefficients back over its own row.  Assembly phase:
-// lanes own new-mode targets and add the derivative / time-integral terms.
+// a4: ADER predictor.  One wavefront per zone group.
+// Node phase: lane = (zone slot, spatial Gauss node); each lane keeps the
+// time-independent part of q at its node in registers, evaluates the time
+// modes from LDS, forms the physical fluxes at every time node and contracts
+// them against the shifted-Legendre time basis.
+// Projection phase: the contracted fluxes of the flux time modes e <= P - 2
+// go to LDS as one row per (zone, e, axis d, variable), with the nodes of the
+// row stored so that axis d is the fastest one.  One lane owns a row and
+// projects it in registers with axis d contracted first, keeping only the
+// coefficients the update uses (degree >= 1 along d); it truncates them to
+// total space-time degree P and applies the derivative along d.  The top
+// flux time mode e = P - 1 only reaches the zone-constant spatial modes (its
+// degree-1 coefficients along each axis), so the node phase folds its axes
+// into one weighted node value per variable and the projection phase sums
+// that row in fixed chunks.
+// Assembly phase: lanes own new-mode targets and add the time-integral
+// combination of the differentiated coefficients.
 // After the last iteration the face-point states for the Riemann solver are
 // evaluated from the final modes.  Blocks are mapped to zone groups so that
 // the blocks one XCD runs (every 8th block) take contiguous zones and share
@@ -318,12 +326,34 @@ struct PredShape {
     static constexpr int MST = Modes<D, P>::NST;
     static constexpr int MT = MST - MS;              // modes with e >= 1
     static constexpr int NE = P;                     // flux time modes feeding a derivative
-    static constexpr int NSLZ = NE * D * NV;         // slices per zone
-    static constexpr int RS = NS + 2;                // slice row stride (doubles), padded against bank conflicts
+    static constexpr int NFULL = (NE - 1) * D * NV;  // projected rows per zone (e <= P - 2)
+    static constexpr int NROWZ = NFULL + NV;         // + one folded row per variable (e = P - 1)
+    static constexpr int RS = NS + 2;                // row stride (elements), padded against bank conflicts
+    static constexpr int NG = binom(P - 1 + D, D);   // differentiated coefficients per row
+    static constexpr int CH = 8;                     // chunk of a folded row summed by one lane
+    static constexpr int NCH = (NS + CH - 1) / CH;
     static constexpr int NPT = 1 << D;               // Gauss points per face (tangential x time)
     static constexpr int NFPZ = D * 2 * NPT;         // face points per zone
     static constexpr int NTGT = ZPW * MT * NV;       // new-mode targets per wavefront
     static constexpr int TPL = (NTGT + 63) / 64;     // targets per lane
+};
+
+// Compact index of a differentiated coefficient (lo, o1, o2) with
+// lo + o1 + o2 <= P - 1 (o2 = 0 in 2D): lo is the degree along the derivative
+// axis, o1 and o2 the degrees along the other axes in increasing axis order.
+template <int D, int P>
+struct GIdx {
+    int at[P][P][P];
+    constexpr GIdx() : at{}
+    {
+        int n = 0;
+        for (int o2 = 0; o2 < P; ++o2)
+            for (int o1 = 0; o1 < P; ++o1)
+                for (int lo = 0; lo < P; ++lo) {
+                    const bool ok = lo + o1 + o2 <= P - 1 && (D == 3 || o2 == 0);
+                    at[lo][o1][o2] = ok ? n++ : -1;
+                }
+    }
 };
 
 constexpr int kXcds = 8;   // MI355X: workgroups are dispatched round-robin over 8 XCDs
@@ -340,82 +370,98 @@ inline unsigned xcd_blocks(long long ngroups)
     return (unsigned)(per * kXcds);
 }
 
-// One target of the new space-time modes held by a lane.
+// One new-mode target held by a lane: where its value goes in the mode
+// buffer, where its differentiated coefficients sit in the rows of the
+// e = 0 flux time mode (one per axis), where the folded row of its variable
+// starts, its time degree and whether its spatial degree is zero.
+template <int D>
 struct Target {
-    int valid, z, v, a, b, c, e;
+    int valid, soff, off[D], top, te, zero;
 };
 
-// In-register L2 projection of one slice: node values row[n] (node index
-// (k*N1 + j)*N1 + i) -> modal coefficients written back to
-// row[(c*N1 + b)*N1 + a] for a + b + c <= P.  The node planes are streamed
-// (k outermost) into the modal accumulators, so only one plane is live.
+// L2 projection weight proj[a][i] for a compile-time a and a lane-varying i.
+template <int P>
+__device__ __forceinline__ double proj_at(int a, int i)
+{
+    constexpr Rules<P> RL{};
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k <= P; ++k)
+        if (i == k) v = RL.proj[a][k];
+    return v;
+}
+
+// One projected row.  Input: node values at row[h + N1 * (o1n + N1 * o2n)],
+// h the node index along the derivative axis.  Output, for every
+// (lo, o1, o2) with lo + o1 + o2 <= P - 1, written to row[GIdx(lo, o1, o2)]:
+//   g = sum_{hi > lo, hi + o1 + o2 <= emax} D[hi][lo] c(hi, o1, o2),
+// c the Gauss L2-projection coefficients in the monic Legendre basis.  The
+// bound emax = P - e truncates the flux to total space-time degree P.
 template <int D, int P, typename T>
-__device__ __forceinline__ void project_slice(T* row)
+__device__ __forceinline__ void project_row(T* row, int emax)
 {
     constexpr int N1 = P + 1;
+    constexpr int NO2 = (D == 3) ? N1 : 1;
     constexpr Rules<P> RL{};
-    if constexpr (D == 3) {
-        T out[N1][N1][N1] = {};   // [c][b][a], a + b + c <= P used
+    constexpr GIdx<D, P> GI{};
+    T c[N1][N1][N1];          // [hi][o1][o2], used for hi >= 1, hi + o1 + o2 <= P
 #pragma unroll
-        for (int k = 0; k < N1; ++k) {
-            T x[N1][N1];
+    for (int p2 = 0; p2 < NO2; ++p2) {
+        T x[N1][N1];          // [o1 node][h]
 #pragma unroll
-            for (int j = 0; j < N1; ++j)
+        for (int o = 0; o < N1; ++o)
 #pragma unroll
-                for (int i = 0; i < N1; ++i) x[j][i] = row[(k * N1 + j) * N1 + i];
-            T t1[N1][N1];   // [j][a]
+            for (int h = 0; h < N1; ++h) x[o][h] = row[(p2 * N1 + o) * N1 + h];
+        T t1[N1][N1];         // [o1 node][hi]
 #pragma unroll
-            for (int j = 0; j < N1; ++j)
+        for (int o = 0; o < N1; ++o)
 #pragma unroll
-                for (int a = 0; a <= P; ++a) {
-                    T s = T(0);
-#pragma unroll
-                    for (int i = 0; i < N1; ++i) s += T(RL.proj[a][i]) * x[j][i];
-                    t1[j][a] = s;
-                }
-#pragma unroll
-            for (int a = 0; a <= P; ++a)
-#pragma unroll
-                for (int b = 0; a + b <= P; ++b) {
-                    T s = T(0);
-#pragma unroll
-                    for (int j = 0; j < N1; ++j) s += T(RL.proj[b][j]) * t1[j][a];
-#pragma unroll
-                    for (int c = 0; a + b + c <= P; ++c) out[c][b][a] += T(RL.proj[c][k]) * s;
-                }
-        }
-#pragma unroll
-        for (int a = 0; a <= P; ++a)
-#pragma unroll
-            for (int b = 0; a + b <= P; ++b)
-#pragma unroll
-                for (int c = 0; a + b + c <= P; ++c) row[(c * N1 + b) * N1 + a] = out[c][b][a];
-    } else {
-        T x[N1][N1];
-#pragma unroll
-        for (int j = 0; j < N1; ++j)
-#pragma unroll
-            for (int i = 0; i < N1; ++i) x[j][i] = row[j * N1 + i];
-        T t1[N1][N1];       // [j][a]
-#pragma unroll
-        for (int j = 0; j < N1; ++j)
-#pragma unroll
-            for (int a = 0; a <= P; ++a) {
+            for (int hi = 1; hi <= P; ++hi) {
                 T s = T(0);
 #pragma unroll
-                for (int i = 0; i < N1; ++i) s += T(RL.proj[a][i]) * x[j][i];
-                t1[j][a] = s;
+                for (int h = 0; h < N1; ++h)
+                    if (RL.proj[hi][h] != 0.0) s += T(RL.proj[hi][h]) * x[o][h];
+                t1[o][hi] = s;
             }
 #pragma unroll
-        for (int a = 0; a <= P; ++a)
+        for (int hi = 1; hi <= P; ++hi)
 #pragma unroll
-            for (int b = 0; a + b <= P; ++b) {
+            for (int o1 = 0; hi + o1 <= P; ++o1) {
                 T s = T(0);
 #pragma unroll
-                for (int j = 0; j < N1; ++j) s += T(RL.proj[b][j]) * t1[j][a];
-                row[b * N1 + a] = s;
+                for (int o = 0; o < N1; ++o)
+                    if (RL.proj[o1][o] != 0.0) s += T(RL.proj[o1][o]) * t1[o][hi];
+                if constexpr (D == 3) {
+#pragma unroll
+                    for (int o2 = 0; hi + o1 + o2 <= P; ++o2) {
+                        const T w = T(RL.proj[o2][p2]);
+                        if (p2 == 0) c[hi][o1][o2] = w * s;
+                        else c[hi][o1][o2] += w * s;
+                    }
+                } else {
+                    c[hi][o1][0] = s;
+                }
             }
     }
+#pragma unroll
+    for (int hi = 1; hi <= P; ++hi)
+#pragma unroll
+        for (int o1 = 0; hi + o1 <= P; ++o1)
+#pragma unroll
+            for (int o2 = 0; o2 < NO2 && hi + o1 + o2 <= P; ++o2)
+                if (hi + o1 + o2 > emax) c[hi][o1][o2] = T(0);
+#pragma unroll
+    for (int o2 = 0; o2 < NO2 && o2 <= P - 1; ++o2)
+#pragma unroll
+        for (int o1 = 0; o1 + o2 <= P - 1; ++o1)
+#pragma unroll
+            for (int lo = 0; lo + o1 + o2 <= P - 1; ++lo) {
+                T s = T(0);
+#pragma unroll
+                for (int hi = lo + 1; hi + o1 + o2 <= P; ++hi)
+                    if (RL.D[hi][lo] != 0.0) s += T(RL.D[hi][lo]) * c[hi][o1][o2];
+                row[GI.at[lo][o1][o2]] = s;
+            }
 }
 
 template <int D, int P, typename T>
@@ -425,12 +471,14 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 {
     using S = PredShape<D, P>;
     constexpr int NV = S::NV, N1 = S::N1, NS = S::NS, ZPW = S::ZPW, RS = S::RS;
-    constexpr int MS = S::MS, MST = S::MST, MT = S::MT, NE = S::NE, NSLZ = S::NSLZ;
+    constexpr int MS = S::MS, MST = S::MST, MT = S::MT, NE = S::NE;
+    constexpr int NFULL = S::NFULL, NROWZ = S::NROWZ, CH = S::CH, NCH = S::NCH;
     constexpr Modes<D, P> M{};
     constexpr Rules<P> RL{};
+    constexpr GIdx<D, P> GI{};
 
     __shared__ T sq[ZPW * MST * NV];
-    __shared__ T sr[ZPW * NSLZ * RS];
+    __shared__ T sr[ZPW * NROWZ * RS];
     __shared__ int sbad[ZPW];
 
     const long long nR = box_size(R);
@@ -463,25 +511,57 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
             pz[a] = (D == 3) ? T(mleg(a, zn)) : T(a == 0 ? 1 : 0);
         }
     }
+    // position of this lane's node in a row whose derivative axis is d: that
+    // axis fastest, then the other axes in increasing order
+    int pos[D];
+    pos[0] = node;
+    if constexpr (D == 3) {
+        pos[1] = jj + N1 * (ii + N1 * kk);
+        pos[2] = kk + N1 * (ii + N1 * jj);
+    } else {
+        pos[1] = jj + N1 * ii;
+    }
+    // top flux time mode: weight of axis d in the folded node value,
+    //   lam_d D[1][0] proj[1][n_d] prod_{other axes} proj[0][n_axis]
+    T kap[D];
+    {
+        const int nd[3] = {ii, jj, kk};
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            double k = RL.D[1][0];
+#pragma unroll
+            for (int ax = 0; ax < D; ++ax) k *= proj_at<P>(ax == d ? 1 : 0, nd[ax]);
+            kap[d] = lam[d] * T(k);
+        }
+    }
     // the new-mode targets this lane accumulates
-    Target tg[S::TPL];
+    Target<D> tg[S::TPL];
 #pragma unroll
     for (int r = 0; r < S::TPL; ++r) {
         const int t = lane + 64 * r;
         tg[r].valid = t < S::NTGT;
         const int tt = tg[r].valid ? t : 0;
-        tg[r].z = tt / (MT * NV);
-        const int rem = tt % (MT * NV), mt = rem / NV;
-        tg[r].v = rem % NV;
-        tg[r].a = tg[r].b = tg[r].c = tg[r].e = 0;
+        const int z = tt / (MT * NV);
+        const int rem = tt % (MT * NV), mt = rem / NV, v = rem % NV;
+        int te = 0, zero = 0, g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
         for (int q = 0; q < MT; ++q)
             if (q == mt) {
-                tg[r].a = M.a[MS + q];
-                tg[r].b = M.b[MS + q];
-                tg[r].c = M.c[MS + q];
-                tg[r].e = M.e[MS + q];
+                const int a = M.a[MS + q], b = M.b[MS + q], c = M.c[MS + q];
+                te = M.e[MS + q];
+                zero = (a + b + c == 0);
+                g0 = GI.at[a][b][c];
+                g1 = GI.at[b][a][c];
+                g2 = (D == 3) ? GI.at[c][a][b] : 0;
             }
+        tg[r].soff = (z * MST + MS + mt) * NV + v;
+        const int base = z * NROWZ * RS;
+        tg[r].off[0] = base + v * RS + g0;
+        tg[r].off[1] = base + (NV + v) * RS + g1;
+        if constexpr (D == 3) tg[r].off[2] = base + (2 * NV + v) * RS + g2;
+        tg[r].top = base + (NFULL + v) * RS;
+        tg[r].te = te;
+        tg[r].zero = zero;
     }
     __syncthreads();
 
@@ -501,18 +581,18 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 
     for (int it = 0; it < P; ++it) {
         const bool first = it == 0;            // first iterate is time-independent
-        const int ne = first ? 1 : NE;
+        const int nfe = first ? 1 : NE - 1;    // projected flux time modes this iteration
         // ---- node phase
         if (active) {
             bool ok = true;
-            T* rz = sr + zs * NSLZ * RS + node;     // slice (e, d, v) at rz[((e*D + d)*NV + v)*RS]
+            T* rz = sr + zs * NROWZ * RS;       // row (e, d, v) at rz[((e*D + d)*NV + v)*RS], folded row v at rz[(NFULL + v)*RS]
             if (first) {
                 T F[D][NV];
                 ok = fluxes<D, T>(Q0, gm1, F);
 #pragma unroll
                 for (int d = 0; d < D; ++d)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) rz[(d * NV + v) * RS] = F[d][v];
+                    for (int v = 0; v < NV; ++v) rz[(d * NV + v) * RS + pos[d]] = F[d][v];
             } else {
                 T Qe[P][NV];                        // time modes e = 1..P at the node
 #pragma unroll
@@ -526,13 +606,16 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 #pragma unroll
                     for (int v = 0; v < NV; ++v) Qe[M.e[m] - 1][v] += qz[m * NV + v] * phi;
                 }
-                T Racc[NE][D][NV];
+                T Racc[NE - 1][D][NV];
+                T Rtop[NV];
 #pragma unroll
-                for (int e = 0; e < NE; ++e)
+                for (int e = 0; e < NE - 1; ++e)
 #pragma unroll
                     for (int d = 0; d < D; ++d)
 #pragma unroll
                         for (int v = 0; v < NV; ++v) Racc[e][d][v] = T(0);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Rtop[v] = T(0);
 #pragma unroll
                 for (int l = 0; l < N1; ++l) {
                     T U[NV];
@@ -546,69 +629,87 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
                     T F[D][NV];
                     ok = fluxes<D, T>(U, gm1, F) && ok;
 #pragma unroll
-                    for (int e = 0; e < NE; ++e)
+                    for (int e = 0; e < NE - 1; ++e)
 #pragma unroll
                         for (int d = 0; d < D; ++d)
 #pragma unroll
                             for (int v = 0; v < NV; ++v) Racc[e][d][v] += T(RL.tproj[e][l]) * F[d][v];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        T s = kap[0] * F[0][v];
+#pragma unroll
+                        for (int d = 1; d < D; ++d) s += kap[d] * F[d][v];
+                        Rtop[v] += T(RL.tproj[NE - 1][l]) * s;
+                    }
                 }
 #pragma unroll
-                for (int e = 0; e < NE; ++e)
+                for (int e = 0; e < NE - 1; ++e)
 #pragma unroll
                     for (int d = 0; d < D; ++d)
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) rz[((e * D + d) * NV + v) * RS] = Racc[e][d][v];
+                        for (int v = 0; v < NV; ++v) rz[((e * D + d) * NV + v) * RS + pos[d]] = Racc[e][d][v];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) rz[(NFULL + v) * RS + node] = Rtop[v];
             }
             if (positivity && !ok) atomicOr(&sbad[zs], 1);
         }
         __syncthreads();
-        // ---- projection phase: one lane per slice
+        // ---- projection phase: one lane per row; chunk sums of the folded rows
         {
-            const int nsl = ZPW * ne * D * NV;
-            for (int s = lane; s < nsl; s += 64) {
-                const int z = s / (ne * D * NV), r = s % (ne * D * NV);
-                project_slice<D, P, T>(sr + (z * NSLZ + r) * RS);
+            const int nfz = nfe * D * NV;
+            for (int s = lane; s < ZPW * nfz; s += 64) {
+                const int z = s / nfz, r = s % nfz;
+                project_row<D, P, T>(sr + (z * NROWZ + r) * RS, P - r / (D * NV));
+            }
+            if (!first) {
+                for (int s = lane; s < ZPW * NV * NCH; s += 64) {
+                    const int z = s / (NV * NCH), r = s % (NV * NCH), v = r / NCH, ch = r % NCH;
+                    T* p = sr + (z * NROWZ + NFULL + v) * RS + ch * CH;
+                    T acc = p[0];
+                    if constexpr (NS % CH == 0) {
+#pragma unroll
+                        for (int i = 1; i < CH; ++i) acc += p[i];
+                    } else {
+#pragma unroll
+                        for (int i = 1; i < CH; ++i)
+                            if (ch * CH + i < NS) acc += p[i];
+                    }
+                    p[0] = acc;
+                }
             }
         }
         __syncthreads();
-        // ---- assembly: derivative along each axis and time integral
-        //   q[t] -= sum_d lam_d sum_e' I[e'][e_t] sum_{a'' > t_d} D[a''][t_d] f_{e',d}[.. a'' ..]
+        // ---- assembly: for target (a, b, c, te), variable v,
+        //   q = -sum_e I[e][te] sum_d lam_d g_{e,d,v}(rotated (a, b, c))
+        //       - I[P-1][te] [a = b = c = 0] (folded row sum of v)
 #pragma unroll
         for (int r = 0; r < S::TPL; ++r) {
-            const Target& tq = tg[r];
+            const Target<D>& tq = tg[r];
             if (!tq.valid) continue;
             T acc = T(0);
 #pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                if (e >= ne || tq.e > e + 1) continue;
+            for (int e = 0; e < NE - 1; ++e) {
+                if (e >= nfe) continue;
                 T ci = T(0);
 #pragma unroll
                 for (int et = 1; et <= P; ++et)
-                    if (tq.e == et) ci = T(RL.I[e][et]);
-                T sum = T(0);
+                    if (tq.te == et) ci = T(RL.I[e][et]);
+                T sum = lam[0] * sr[tq.off[0] + e * D * NV * RS];
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const int td = (d == 0) ? tq.a : (d == 1 ? tq.b : tq.c);
-                    const int others = tq.a + tq.b + tq.c - td;
-                    const T* f = sr + (tq.z * NSLZ + (e * D + d) * NV + tq.v) * RS;
-                    T sd = T(0);
-#pragma unroll
-                    for (int hi = 1; hi <= P; ++hi) {
-                        if (hi > td && hi + others + e <= P) {
-                            T cd = T(0);
-#pragma unroll
-                            for (int lo = 0; lo < P; ++lo)
-                                if (td == lo) cd = T(RL.D[hi][lo]);
-                            const int ia = (d == 0) ? hi : tq.a, ib = (d == 1) ? hi : tq.b, ic = (d == 2) ? hi : tq.c;
-                            const int off = (D == 3) ? (ic * N1 + ib) * N1 + ia : ib * N1 + ia;
-                            sd += cd * f[off];
-                        }
-                    }
-                    sum += lam[d] * sd;
-                }
+                for (int d = 1; d < D; ++d) sum += lam[d] * sr[tq.off[d] + e * D * NV * RS];
                 acc += ci * sum;
             }
-            sq[(tq.z * MST + MS + (lane + 64 * r) % (MT * NV) / NV) * NV + tq.v] = -acc;
+            if (!first) {
+                T ct = T(0);
+#pragma unroll
+                for (int et = 1; et <= P; ++et)
+                    if (tq.te == et && tq.zero) ct = T(RL.I[NE - 1][et]);
+                T s = sr[tq.top];
+#pragma unroll
+                for (int ch = 1; ch < NCH; ++ch) s += sr[tq.top + ch * CH];
+                acc += ct * s;
+            }
+            sq[tq.soff] = -acc;
         }
         __syncthreads();
     }
