@@ -43,18 +43,29 @@ def spatial_eval_fma(D, L, N1):
     return N1 * _binom(L + 2, 2) + N1 ** 2 * (L + 1)
 
 
+def needed_proj_fma(D, L, N1):
+    """FMAs to project one flux row onto the coefficients its derivative needs:
+    degree >= 1 along the derivative axis and total degree <= L, by sum
+    factorisation with the derivative axis contracted first."""
+    if D == 3:
+        return N1 ** 3 * L + N1 ** 2 * (L * (L + 1) // 2) + N1 * _binom(L + 2, 3)
+    return N1 ** 2 * L + N1 * (L * (L + 1) // 2)
+
+
 def predictor_flops(D, P):
-    """Algorithmic FP64 flops of the ADER predictor for one zone (FMA = 2).
+    """Algorithmic flops of the ADER predictor for one zone (FMA = 2).
 
     Formulation: P Picard iterations; the first on the spatial nodes only
     (the initial iterate does not depend on time), the others on the
     (P+1)^(D+1) space-time Gauss nodes: evaluate the space-time modes by sum
     factorisation (spatial transform of each time mode, Horner in time),
     physical fluxes of all D axes, contraction against the P time modes that
-    feed a derivative, sum-factorised spatial L2 projection of each
-    (axis, time mode, variable), derivative / time-integral assembly; then the
-    face-point states (normal-axis contraction, tangential x time transform
-    at 2^D points) for the Riemann solver.  Division counted as one flop.
+    feed a derivative, and for each (axis d, flux time mode e, variable) the
+    L2 projection onto the only coefficients the update uses (degree >= 1
+    along d, total space-time degree <= P), the derivative along d and the
+    time-integral assembly of the new modes; then the face-point states
+    (normal-axis contraction, tangential x time transform at 2^D points) for
+    the Riemann solver.  Division counted as one flop.
     """
     N1, NV = P + 1, D + 2
     ns, nst = _binom(P + D, D), _binom(P + D + 1, D + 1)
@@ -71,10 +82,18 @@ def predictor_flops(D, P):
             nodes = N1 ** (D + 1)
             ne = P
             tcon = nodes * D * ne * NV                # FMAs
-        proj = D * NV * sum(spatial_eval_fma(D, P - e, N1) for e in range(ne))
-        # derivative / time-integral assembly: one FMA per (axis, source, target) term
+        proj = D * NV * sum(needed_proj_fma(D, P - e, N1) for e in range(ne))
+        # derivative along d of the kept coefficients: one FMA per (hi > lo) pair
+        deriv = 0
+        for e in range(ne):
+            L = P - e
+            for s in range(L):                     # s = degree along the other axes
+                nother = s + 1 if D == 3 else 1
+                deriv += nother * sum(L - s - lo for lo in range(L - s))
+        deriv *= D * NV
+        # time-integral assembly: one FMA per (axis, flux time mode, target) term
         asm = D * (nst - ns) * NV * P
-        total += 2 * (ev + tcon + proj + asm) + nodes * flux_node
+        total += 2 * (ev + tcon + proj + deriv + asm) + nodes * flux_node
     # face-point states: per face side contract the normal axis, then the
     # (D-1 spatial + time) polynomial of degree P at 2^D points
     face_side = nst + sum(2 ** (k + 1) * _binom(P + D - k, D - k) for k in range(D))
@@ -101,6 +120,58 @@ def traffic_record():
     if rec.get("kernel_hash") != kernel_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+PMC_COMMAND = ("export TMPDIR=/tmp; timeout -s KILL 240 rocprofv3 --pmc {ctr} --kernel-include-regex "
+               "\"k_predict|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --steps 2 "
+               "--warmup 0 --no-cpu-baseline --no-mixed --copy-calibration")
+
+
+def write_traffic(fetch_csv, write_csv, n=128):
+    """Traffic record of the FP64 predictor from two rocprofv3 counter runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of this script with
+    --copy-calibration: each counter is scaled by what it reads for the plain
+    copy of 2^27 doubles (1 GiB read, 1 GiB written) in the same run."""
+    import csv
+    from collections import defaultdict
+
+    def per_dispatch(path, counter):
+        acc = defaultdict(float)
+        names = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                acc[r["Dispatch_Id"]] += float(r["Counter_Value"])
+                names[r["Dispatch_Id"]] = r["Kernel_Name"]
+        pred = [v * 1024 for d, v in acc.items() if "k_predict<3, 3, double>" in names[d]]
+        copy = [v * 1024 for d, v in acc.items() if "elementwise" in names[d]]
+        if not pred or not copy:
+            raise SystemExit(f"{path}: no predictor or copy dispatch with {counter}")
+        return sum(pred) / len(pred), sum(copy) / len(copy)
+
+    gib = float(1 << 30)
+    fetch, fcopy = per_dispatch(fetch_csv, "FETCH_SIZE")
+    write, wcopy = per_dispatch(write_csv, "WRITE_SIZE")
+    fs, ws = gib / fcopy, gib / wcopy
+    zones = (n + 2) ** 3
+    rec = {
+        "kernel": "k_predict<3,3> (FP64)",
+        "workload": f"3D vortex + density modes, {n}^3, order 4",
+        "kernel_hash": kernel_hash(),
+        "bytes_per_launch": fetch * fs + write * ws,
+        "fetch_bytes_per_launch": fetch * fs,
+        "write_bytes_per_launch": write * ws,
+        "fetch_scale": fs,
+        "write_scale": ws,
+        "algorithmic_bytes_per_launch": zones * (20 + 48) * 5 * 8,
+        "commands": [PMC_COMMAND.format(ctr="FETCH_SIZE", tag="fetch"),
+                     PMC_COMMAND.format(ctr="WRITE_SIZE", tag="write")],
+        "calibration": "plain elementwise copy of 2^27 doubles (1 GiB read + 1 GiB written) in the same runs",
+    }
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def cpu_baseline(order, seconds):
@@ -174,7 +245,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 2 x 1 GiB (known bytes) to "
                          "calibrate the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the predictor traffic record from two rocprofv3 counter files and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU path (halo exchange and a min "
               "all-reduce of dt) is a design note, not part of this build.", file=sys.stderr)
