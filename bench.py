@@ -215,15 +215,20 @@ def mixed_run(hog, torch, pb, order, steps, ref, gate=None):
     g.advance(2)
     g.set_state(pb.U)
     torch.cuda.synchronize()
+    g.profile(True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     g.advance(steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    prof = g.profile_read()
+    g.profile(False)
     U = g.get_state()
     rel = float(np.abs(U - ref).sum() / np.abs(ref).sum())
     rho_l1 = float(np.abs(U[0] - ref[0]).mean())
     out = {"value": pb.U[0].size * steps / el, "unit": UNIT, "ms_per_step": el * 1e3 / steps,
-           "dtype": "f32+f64", "rel_l1_vs_fp64": rel, "density_l1_vs_fp64": rho_l1}
+           "dtype": "f32+f64", "rel_l1_vs_fp64": rel, "density_l1_vs_fp64": rho_l1,
+           "stages_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items()}}
     if gate is not None:
         _, flags = g.gate_eval()
         out["gate_theta"] = gate[1]

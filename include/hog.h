@@ -154,10 +154,11 @@ int hog_debug_tap(hog_grid* g, int tap, void* dst, size_t bytes);
 
 /* Stage timing with HIP events recorded on the handle's stream around every
  * stage of every subsequent step: 0 ghost fill, 1 reconstruction sweeps,
- * 2 ADER predictor, 3 Riemann solver, 4 update + CFL (HOG_NSTAGES).  Used to
+ * 2 ADER predictor, 3 Riemann solver, 4 update + CFL, 5 learned-gate
+ * inference (only with a gate set) (HOG_NSTAGES).  Used to
  * split step time the way the paper splits out the predictor (Sec. III.1,
  * Table III).  enable = 0 stops recording.  Errors: HOG_EINVAL, HOG_EDEVICE. */
-#define HOG_NSTAGES 5
+#define HOG_NSTAGES 6
 int hog_profile_enable(hog_grid* g, int enable);
 
 /* Total milliseconds and launch count per stage since the last enable/read

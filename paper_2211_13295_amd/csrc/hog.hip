@@ -235,13 +235,14 @@ int enqueue_step_t(hog_grid* g, double dt_user)
                                                        g->cfg.bc[1], g->cfg.bc[2]);
     }
     {
-        StageMark m(g, 1);
         const unsigned char* gf = nullptr;
         if (g->gate_on) {
+            StageMark mg(g, 5);
             k_gate_infer<D><<<nblocks(box_size(L.I), 16), 64, 0, s>>>(
                 Uc, L.pad, L.I, static_cast<const GateParams<D>*>(g->gate), g->flags, nullptr);
             gf = g->flags;
         }
+        StageMark m(g, 1);
         k_recon_x<D, P, T><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa, gf, L.I);
         k_recon_y<D, P, T><<<nblocks(box_size(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa, gf, L.I);
         if constexpr (D == 3)

@@ -464,6 +464,96 @@ __device__ __forceinline__ void project_row(T* row, int emax)
             }
 }
 
+// Value held by the other lane of an even/odd lane pair (DPP quad_perm 1,0,3,2).
+__device__ __forceinline__ double pair_swap(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0xB1, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float pair_swap(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
+// project_row in 3D by a lane pair: lane `half` of the pair takes the node
+// planes half, half + 2, ... along the second other axis, the pair adds its
+// two partial sums (the same two numbers on both lanes, so both hold the same
+// result) and both lanes write the same differentiated coefficients.
+template <int P, typename T>
+__device__ __forceinline__ void project_row_pair(T* row, int emax, int half)
+{
+    constexpr int N1 = P + 1;
+    constexpr int NPL = (N1 + 1) / 2;   // node planes per lane
+    constexpr Rules<P> RL{};
+    constexpr GIdx<3, P> GI{};
+    T c[N1][N1][N1];          // [hi][o1][o2], used for hi >= 1, hi + o1 + o2 <= P
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+        const int p2 = 2 * t + half;
+        const bool live = (N1 % 2 == 0) || 2 * t + 1 < N1 || half == 0;
+        T w[N1];              // projection weights of this lane's plane
+#pragma unroll
+        for (int o2 = 0; o2 <= P; ++o2) {
+            const T w0 = T(RL.proj[o2][2 * t]);
+            const T w1 = (2 * t + 1 < N1) ? T(RL.proj[o2][2 * t + 1]) : T(0);
+            w[o2] = half ? w1 : w0;
+        }
+        T x[N1][N1];          // [o1 node][h]
+#pragma unroll
+        for (int o = 0; o < N1; ++o)
+#pragma unroll
+            for (int h = 0; h < N1; ++h) x[o][h] = live ? row[(p2 * N1 + o) * N1 + h] : T(0);
+        T t1[N1][N1];         // [o1 node][hi]
+#pragma unroll
+        for (int o = 0; o < N1; ++o)
+#pragma unroll
+            for (int hi = 1; hi <= P; ++hi) {
+                T s = T(0);
+#pragma unroll
+                for (int h = 0; h < N1; ++h)
+                    if (RL.proj[hi][h] != 0.0) s += T(RL.proj[hi][h]) * x[o][h];
+                t1[o][hi] = s;
+            }
+#pragma unroll
+        for (int hi = 1; hi <= P; ++hi)
+#pragma unroll
+            for (int o1 = 0; hi + o1 <= P; ++o1) {
+                T s = T(0);
+#pragma unroll
+                for (int o = 0; o < N1; ++o)
+                    if (RL.proj[o1][o] != 0.0) s += T(RL.proj[o1][o]) * t1[o][hi];
+#pragma unroll
+                for (int o2 = 0; hi + o1 + o2 <= P; ++o2) {
+                    if (t == 0) c[hi][o1][o2] = w[o2] * s;
+                    else c[hi][o1][o2] += w[o2] * s;
+                }
+            }
+    }
+#pragma unroll
+    for (int hi = 1; hi <= P; ++hi)
+#pragma unroll
+        for (int o1 = 0; hi + o1 <= P; ++o1)
+#pragma unroll
+            for (int o2 = 0; hi + o1 + o2 <= P; ++o2) {
+                const T own = c[hi][o1][o2];
+                c[hi][o1][o2] = own + pair_swap(own);
+                if (hi + o1 + o2 > emax) c[hi][o1][o2] = T(0);
+            }
+#pragma unroll
+    for (int o2 = 0; o2 <= P - 1; ++o2)
+#pragma unroll
+        for (int o1 = 0; o1 + o2 <= P - 1; ++o1)
+#pragma unroll
+            for (int lo = 0; lo + o1 + o2 <= P - 1; ++lo) {
+                T s = T(0);
+#pragma unroll
+                for (int hi = lo + 1; hi + o1 + o2 <= P; ++hi)
+                    if (RL.D[hi][lo] != 0.0) s += T(RL.D[hi][lo]) * c[hi][o1][o2];
+                row[GI.at[lo][o1][o2]] = s;
+            }
+}
+
 template <int D, int P, typename T>
 __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box R,
                                                    StepInfo* __restrict__ info, double gamma, int positivity,
@@ -654,12 +744,22 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
             if (positivity && !ok) atomicOr(&sbad[zs], 1);
         }
         __syncthreads();
-        // ---- projection phase: one lane per row; chunk sums of the folded rows
+        // ---- projection phase: one lane (2D) or lane pair (3D) per row; chunk
+        //      sums of the folded rows
         {
             const int nfz = nfe * D * NV;
-            for (int s = lane; s < ZPW * nfz; s += 64) {
-                const int z = s / nfz, r = s % nfz;
-                project_row<D, P, T>(sr + (z * NROWZ + r) * RS, P - r / (D * NV));
+            if constexpr (D == 3) {
+                static_assert(2 * ZPW * NFULL <= 64, "one lane pair per projected row");
+                const int s = lane >> 1;
+                if (s < ZPW * nfz) {
+                    const int z = s / nfz, r = s % nfz;
+                    project_row_pair<P, T>(sr + (z * NROWZ + r) * RS, P - r / (D * NV), lane & 1);
+                }
+            } else {
+                for (int s = lane; s < ZPW * nfz; s += 64) {
+                    const int z = s / nfz, r = s % nfz;
+                    project_row<D, P, T>(sr + (z * NROWZ + r) * RS, P - r / (D * NV));
+                }
             }
             if (!first) {
                 for (int s = lane; s < ZPW * NV * NCH; s += 64) {

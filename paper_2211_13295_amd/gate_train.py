@@ -6,7 +6,8 @@ density modes (periodic) and the multi-blast (outflow) -- at several steps of
 each run; label smooth <=> the largest |omega_k/gamma_k - 1| over the
 variables and the 1D applications centred at the zone is <= 0.25.  The set is
 stratified to equal class counts, split 90/10 (seeded), and the network is
-trained with the library's kernels (hog_mlp_step: Adam, batch 4096).  The
+trained with the library's kernels (hog_mlp_step: Adam, batch 4096, learning
+rate decayed to zero on a cosine).  The
 probability threshold is the smallest one whose false-smooth rate on the
 held-out 10% (non-smooth zones predicted smooth / non-smooth zones) is at
 most the target.
@@ -66,8 +67,9 @@ def train(hog, torch, X, y, epochs, lr, batch, seed, log):
     t0 = time.time()
     for it in range(steps):
         idx = torch.randint(0, n, (batch,), generator=gen).cuda()
-        want = (it % 200 == 0) or it == steps - 1
-        loss = m.step(X[idx].contiguous(), y[idx].contiguous(), None, lr=lr, want_loss=want)
+        want = (it % 1000 == 0) or it == steps - 1
+        lr_t = lr * 0.5 * (1.0 + np.cos(np.pi * it / steps))      # cosine decay to zero
+        loss = m.step(X[idx].contiguous(), y[idx].contiguous(), None, lr=lr_t, want_loss=want)
         if want:
             log(f"  step {it}/{steps} loss {loss:.4f} ({time.time() - t0:.1f} s)")
     return m
@@ -82,7 +84,7 @@ def main(argv=None):
     ap.add_argument("--steps-between", type=int, default=10)
     ap.add_argument("--per-snapshot", type=int, default=600000)
     ap.add_argument("--samples", type=int, default=5000000)
-    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--target-fsr", type=float, default=1e-3)

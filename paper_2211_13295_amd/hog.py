@@ -229,7 +229,7 @@ class Grid:
         _check(load().hog_debug_tap(self._h, which, out.ctypes.data_as(C.c_void_p), out.nbytes))
         return out
 
-    STAGES = ("ghost", "reconstruction", "predictor", "riemann", "update")
+    STAGES = ("ghost", "reconstruction", "predictor", "riemann", "update", "gate")
 
     def profile(self, enable=True):
         _check(load().hog_profile_enable(self._h, int(bool(enable))))
