@@ -145,7 +145,7 @@ def write_traffic(fetch_csv, write_csv, n=128):
                 acc[r["Dispatch_Id"]] += float(r["Counter_Value"])
                 names[r["Dispatch_Id"]] = r["Kernel_Name"]
         pred = [v * 1024 for d, v in acc.items() if "k_predict<3, 3, double>" in names[d]]
-        copy = [v * 1024 for d, v in acc.items() if "elementwise" in names[d]]
+        copy = [v * 1024 for d, v in acc.items() if "MulFunctor" in names[d]]   # the x * 1.0 copies
         if not pred or not copy:
             raise SystemExit(f"{path}: no predictor or copy dispatch with {counter}")
         return sum(pred) / len(pred), sum(copy) / len(copy)

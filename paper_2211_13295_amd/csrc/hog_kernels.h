@@ -379,6 +379,68 @@ struct Target {
     int valid, soff, off[D], top, te, zero;
 };
 
+// Per-lane constants of the predictor, built at compile time and read from
+// constant memory at kernel start (one record per lane of the wavefront):
+// the monic Legendre basis at the lane's node along x, y, z, the node weight
+// of the folded top flux time mode (without lam_d), the node's position in
+// the rows of each derivative axis, and the new-mode targets the lane owns.
+template <int D, int P>
+struct LaneRec {
+    static constexpr int TPL = PredShape<D, P>::TPL;
+    double bas[3][P + 1];
+    double kapb[3];
+    int pos[3];
+    int soff[TPL], off[TPL][3], top[TPL], te[TPL], zero[TPL], valid[TPL];
+};
+
+template <int D, int P>
+struct LaneTable {
+    LaneRec<D, P> r[64];
+    constexpr LaneTable() : r{}
+    {
+        using S = PredShape<D, P>;
+        constexpr int N1 = P + 1, NS = S::NS, NV = S::NV, MS = S::MS, MST = S::MST, MT = S::MT;
+        const Rules<P> RL{};
+        const Modes<D, P> M{};
+        const GIdx<D, P> GI{};
+        for (int lane = 0; lane < 64; ++lane) {
+            LaneRec<D, P>& q = r[lane];
+            const int node = lane % NS;
+            const int nd[3] = {node % N1, (node / N1) % N1, D == 3 ? node / (N1 * N1) : 0};
+            for (int ax = 0; ax < 3; ++ax)
+                for (int a = 0; a <= P; ++a)
+                    q.bas[ax][a] = (ax < D) ? RL.px[a][nd[ax]] : (a == 0 ? 1.0 : 0.0);
+            for (int d = 0; d < 3; ++d) {
+                double k = RL.D[1][0];
+                for (int ax = 0; ax < D; ++ax) k *= RL.proj[ax == d ? 1 : 0][nd[ax]];
+                q.kapb[d] = (d < D) ? k : 0.0;
+            }
+            q.pos[0] = node;
+            q.pos[1] = (D == 3) ? nd[1] + N1 * (nd[0] + N1 * nd[2]) : nd[1] + N1 * nd[0];
+            q.pos[2] = (D == 3) ? nd[2] + N1 * (nd[0] + N1 * nd[1]) : 0;
+            for (int t = 0; t < S::TPL; ++t) {
+                const int g = lane + 64 * t;
+                const int valid = g < S::NTGT;
+                const int gg = valid ? g : 0;
+                const int z = gg / (MT * NV), rem = gg % (MT * NV), mt = rem / NV, v = rem % NV;
+                const int a = M.a[MS + mt], b = M.b[MS + mt], c = M.c[MS + mt];
+                const int base = z * S::NROWZ * S::RS;
+                q.valid[t] = valid;
+                q.soff[t] = (z * MST + MS + mt) * NV + v;
+                q.off[t][0] = base + v * S::RS + GI.at[a][b][c];
+                q.off[t][1] = base + (NV + v) * S::RS + GI.at[b][a][c];
+                q.off[t][2] = (D == 3) ? base + (2 * NV + v) * S::RS + GI.at[c][a][b] : 0;
+                q.top[t] = base + (S::NFULL + v) * S::RS;
+                q.te[t] = M.e[MS + mt];
+                q.zero[t] = (a + b + c == 0);
+            }
+        }
+    }
+};
+
+template <int D, int P>
+__constant__ LaneTable<D, P> kLaneTable = LaneTable<D, P>();
+
 // L2 projection weight proj[a][i] for a compile-time a and a lane-varying i.
 template <int P>
 __device__ __forceinline__ double proj_at(int a, int i)
@@ -561,11 +623,10 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 {
     using S = PredShape<D, P>;
     constexpr int NV = S::NV, N1 = S::N1, NS = S::NS, ZPW = S::ZPW, RS = S::RS;
-    constexpr int MS = S::MS, MST = S::MST, MT = S::MT, NE = S::NE;
+    constexpr int MS = S::MS, MST = S::MST, NE = S::NE;
     constexpr int NFULL = S::NFULL, NROWZ = S::NROWZ, CH = S::CH, NCH = S::NCH;
     constexpr Modes<D, P> M{};
     constexpr Rules<P> RL{};
-    constexpr GIdx<D, P> GI{};
 
     __shared__ T sq[ZPW * MST * NV];
     __shared__ T sr[ZPW * NROWZ * RS];
@@ -590,68 +651,35 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
     const int zs = lane / NS;
     const int node = lane % NS;
     const bool active = zs < ZPW;
-    const int ii = node % N1, jj = (node / N1) % N1, kk = (D == 3) ? node / (N1 * N1) : 0;
+    const LaneRec<D, P>& LR = kLaneTable<D, P>.r[lane];
     T px[P + 1], py[P + 1], pz[P + 1];
-    {
-        const double xn = gl_node(N1, ii), yn = gl_node(N1, jj), zn = gl_node(N1, kk);
 #pragma unroll
-        for (int a = 0; a <= P; ++a) {
-            px[a] = T(mleg(a, xn));
-            py[a] = T(mleg(a, yn));
-            pz[a] = (D == 3) ? T(mleg(a, zn)) : T(a == 0 ? 1 : 0);
-        }
+    for (int a = 0; a <= P; ++a) {
+        px[a] = T(LR.bas[0][a]);
+        py[a] = T(LR.bas[1][a]);
+        pz[a] = T(LR.bas[2][a]);
     }
     // position of this lane's node in a row whose derivative axis is d: that
     // axis fastest, then the other axes in increasing order
     int pos[D];
-    pos[0] = node;
-    if constexpr (D == 3) {
-        pos[1] = jj + N1 * (ii + N1 * kk);
-        pos[2] = kk + N1 * (ii + N1 * jj);
-    } else {
-        pos[1] = jj + N1 * ii;
-    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) pos[d] = LR.pos[d];
     // top flux time mode: weight of axis d in the folded node value,
     //   lam_d D[1][0] proj[1][n_d] prod_{other axes} proj[0][n_axis]
     T kap[D];
-    {
-        const int nd[3] = {ii, jj, kk};
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            double k = RL.D[1][0];
-#pragma unroll
-            for (int ax = 0; ax < D; ++ax) k *= proj_at<P>(ax == d ? 1 : 0, nd[ax]);
-            kap[d] = lam[d] * T(k);
-        }
-    }
+    for (int d = 0; d < D; ++d) kap[d] = lam[d] * T(LR.kapb[d]);
     // the new-mode targets this lane accumulates
     Target<D> tg[S::TPL];
 #pragma unroll
     for (int r = 0; r < S::TPL; ++r) {
-        const int t = lane + 64 * r;
-        tg[r].valid = t < S::NTGT;
-        const int tt = tg[r].valid ? t : 0;
-        const int z = tt / (MT * NV);
-        const int rem = tt % (MT * NV), mt = rem / NV, v = rem % NV;
-        int te = 0, zero = 0, g0 = 0, g1 = 0, g2 = 0;
+        tg[r].valid = LR.valid[r];
+        tg[r].soff = LR.soff[r];
 #pragma unroll
-        for (int q = 0; q < MT; ++q)
-            if (q == mt) {
-                const int a = M.a[MS + q], b = M.b[MS + q], c = M.c[MS + q];
-                te = M.e[MS + q];
-                zero = (a + b + c == 0);
-                g0 = GI.at[a][b][c];
-                g1 = GI.at[b][a][c];
-                g2 = (D == 3) ? GI.at[c][a][b] : 0;
-            }
-        tg[r].soff = (z * MST + MS + mt) * NV + v;
-        const int base = z * NROWZ * RS;
-        tg[r].off[0] = base + v * RS + g0;
-        tg[r].off[1] = base + (NV + v) * RS + g1;
-        if constexpr (D == 3) tg[r].off[2] = base + (2 * NV + v) * RS + g2;
-        tg[r].top = base + (NFULL + v) * RS;
-        tg[r].te = te;
-        tg[r].zero = zero;
+        for (int d = 0; d < D; ++d) tg[r].off[d] = LR.off[r][d];
+        tg[r].top = LR.top[r];
+        tg[r].te = LR.te[r];
+        tg[r].zero = LR.zero[r];
     }
     __syncthreads();
 
