@@ -37,11 +37,29 @@ __device__ __forceinline__ bool admissible(const T* U, T gm1)
 
 // Physical fluxes of the Euler equations along all D axes at one point;
 // returns whether the state is admissible (rho > 0, p > 0, finite).
+// Reciprocal from the hardware estimate refined by Newton steps
+// r <- r + r (1 - x r): two for FP64, one for FP32 (within a few ulp of 1/x;
+// 0, negative or non-finite x give a non-finite or negative result, which
+// the admissibility check below rejects).
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+
 template <int D, typename T = double>
 __device__ __forceinline__ bool fluxes(const T* U, T gm1, T (*F)[D + 2])
 {
     const T rho = U[0];
-    const T ir = T(1) / rho;
+    const T ir = recip(rho);
     T u[D];
     T ke = T(0);
 #pragma unroll
