@@ -48,34 +48,43 @@ __device__ __forceinline__ uint16_t f2bf(float x)
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ __forceinline__ float bfround(float x) { return bf2f(f2bf(x)); }
 
-// Features of zone (i,j,k) from the padded state: per variable the 13-zone
-// cross (centre, x-2, x-1, x+1, x+2, y-2, ..., z+2), centred on the zone value
-// and scaled by (max - min + 1e-12 max(1, |centre|)), in FP64, then FP32.
+// Features of variable v of zone (i,j,k) from the padded state: the 13-zone
+// cross (centre, x-2, x-1, x+1, x+2, y-2, ..., z+2; 9 zones in 2D), centred on
+// the zone value and scaled by (max - min + 1e-12 max(1, |centre|)), in FP64,
+// then FP32.
+template <int D>
+__device__ __forceinline__ void gate_features_var(const double* __restrict__ U, const Pad& p, int i, int j, int k,
+                                                  int v, float* f)
+{
+    using G = GateShape<D>;
+    const long long c0 = pad_index(p, i, j, k);
+    const long long st[3] = {1, p.np[0], (long long)p.np[0] * p.np[1]};
+    const double* u = U + v * p.vs + c0;
+    double val[G::NC];
+    val[0] = u[0];
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        val[1 + 4 * ax + 0] = u[-2 * st[ax]];
+        val[1 + 4 * ax + 1] = u[-1 * st[ax]];
+        val[1 + 4 * ax + 2] = u[1 * st[ax]];
+        val[1 + 4 * ax + 3] = u[2 * st[ax]];
+    }
+    double mx = val[0], mn = val[0];
+#pragma unroll
+    for (int s = 1; s < G::NC; ++s) { mx = fmax(mx, val[s]); mn = fmin(mn, val[s]); }
+    const double scale = mx - mn + 1e-12 * fmax(1.0, fabs(val[0]));
+#pragma unroll
+    for (int s = 0; s < G::NC; ++s) f[s] = (float)((val[s] - val[0]) / scale);
+}
+
+// All features of zone (i,j,k), ordered [variable][cross].
 template <int D>
 __device__ __forceinline__ void gate_features(const double* __restrict__ U, const Pad& p, int i, int j, int k,
                                               float* f)
 {
     using G = GateShape<D>;
-    const long long c0 = pad_index(p, i, j, k);
-    const long long st[3] = {1, p.np[0], (long long)p.np[0] * p.np[1]};
 #pragma unroll
-    for (int v = 0; v < G::NV; ++v) {
-        double val[G::NC];
-        val[0] = U[v * p.vs + c0];
-#pragma unroll
-        for (int ax = 0; ax < D; ++ax) {
-            val[1 + 4 * ax + 0] = U[v * p.vs + c0 - 2 * st[ax]];
-            val[1 + 4 * ax + 1] = U[v * p.vs + c0 - 1 * st[ax]];
-            val[1 + 4 * ax + 2] = U[v * p.vs + c0 + 1 * st[ax]];
-            val[1 + 4 * ax + 3] = U[v * p.vs + c0 + 2 * st[ax]];
-        }
-        double mx = val[0], mn = val[0];
-#pragma unroll
-        for (int s = 1; s < G::NC; ++s) { mx = fmax(mx, val[s]); mn = fmin(mn, val[s]); }
-        const double scale = mx - mn + 1e-12 * fmax(1.0, fabs(val[0]));
-#pragma unroll
-        for (int s = 0; s < G::NC; ++s) f[v * G::NC + s] = (float)((val[s] - val[0]) / scale);
-    }
+    for (int v = 0; v < G::NV; ++v) gate_features_var<D>(U, p, i, j, k, v, f + v * G::NC);
 }
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
@@ -96,20 +105,24 @@ __global__ __launch_bounds__(64) void k_gate_infer(const double* __restrict__ U,
     const long long N = box_size(I);
     const int lane = threadIdx.x;
     const long long z0 = (long long)blockIdx.x * 16;
-    if (lane < 16) {
-        const long long z = z0 + lane;
-        float f[G::NF];
+    // features: one (zone, variable) per lane and round
+    for (int t = lane; t < 16 * G::NV; t += 64) {
+        const int zl = t & 15, v = t >> 4;
+        const long long z = z0 + zl;
+        float f[G::NC];
         if (z < N) {
             int i, j, k;
             box_ijk(I, z, i, j, k);
-            gate_features<D>(U, p, i, j, k, f);
+            gate_features_var<D>(U, p, i, j, k, v, f);
         } else {
 #pragma unroll
-            for (int q = 0; q < G::NF; ++q) f[q] = 0.0f;
+            for (int q = 0; q < G::NC; ++q) f[q] = 0.0f;
         }
 #pragma unroll
-        for (int q = 0; q < G::NFP; ++q) sx[lane][q] = (q < G::NF) ? f2bf(f[q]) : (uint16_t)0;
+        for (int q = 0; q < G::NC; ++q) sx[zl][v * G::NC + q] = f2bf(f[q]);
     }
+    for (int t = lane; t < 16 * (G::NFP - G::NF); t += 64)
+        sx[t / (G::NFP - G::NF)][G::NF + t % (G::NFP - G::NF)] = (uint16_t)0;
     __syncthreads();
     const int r = lane & 15, g4 = lane >> 4;
     // layer 1: [16 x NFP] x [NFP x 64]

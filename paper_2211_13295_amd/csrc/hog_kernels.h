@@ -379,67 +379,65 @@ struct Target {
     int valid, soff, off[D], top, te, zero;
 };
 
-// Per-lane constants of the predictor, built at compile time and read from
-// constant memory at kernel start (one record per lane of the wavefront):
-// the monic Legendre basis at the lane's node along x, y, z, the node weight
-// of the folded top flux time mode (without lam_d), the node's position in
-// the rows of each derivative axis, and the new-mode targets the lane owns.
-template <int D, int P>
-struct LaneRec {
-    static constexpr int TPL = PredShape<D, P>::TPL;
-    double bas[3][P + 1];
-    double kapb[3];
-    int pos[3];
-    int soff[TPL], off[TPL][3], top[TPL], te[TPL], zero[TPL], valid[TPL];
+// Constants of the predictor lanes, built at compile time and read from
+// constant memory at kernel start.
+// NodeRows: for each Gauss node index i along an axis, the monic Legendre
+// basis at x_i followed by the projection weights proj[0][i] and proj[1][i]
+// (a few distinct rows shared by all lanes, so the loads coalesce).
+template <int P>
+struct NodeRows {
+    double r[P + 1][P + 3];
+    constexpr NodeRows() : r{}
+    {
+        const Rules<P> RL{};
+        for (int i = 0; i <= P; ++i) {
+            for (int a = 0; a <= P; ++a) r[i][a] = RL.px[a][i];
+            r[i][P + 1] = RL.proj[0][i];
+            r[i][P + 2] = RL.proj[1][i];
+        }
+    }
 };
 
+template <int P>
+__constant__ NodeRows<P> kNodeRows = NodeRows<P>();
+
+// TargetTable: the new-mode targets of each lane, three packed words per
+// target: (offset for axis 0) | (offset for axis 1) << 16, (offset for axis 2)
+// | (folded row) << 16, (mode-buffer index) | te << 16 | zero << 20 | valid << 21.
 template <int D, int P>
-struct LaneTable {
-    LaneRec<D, P> r[64];
-    constexpr LaneTable() : r{}
+struct TargetTable {
+    static constexpr int TPL = PredShape<D, P>::TPL;
+    int t[64][TPL][3];
+    constexpr TargetTable() : t{}
     {
         using S = PredShape<D, P>;
-        constexpr int N1 = P + 1, NS = S::NS, NV = S::NV, MS = S::MS, MST = S::MST, MT = S::MT;
-        const Rules<P> RL{};
+        constexpr int NV = S::NV, MS = S::MS, MST = S::MST, MT = S::MT;
         const Modes<D, P> M{};
         const GIdx<D, P> GI{};
-        for (int lane = 0; lane < 64; ++lane) {
-            LaneRec<D, P>& q = r[lane];
-            const int node = lane % NS;
-            const int nd[3] = {node % N1, (node / N1) % N1, D == 3 ? node / (N1 * N1) : 0};
-            for (int ax = 0; ax < 3; ++ax)
-                for (int a = 0; a <= P; ++a)
-                    q.bas[ax][a] = (ax < D) ? RL.px[a][nd[ax]] : (a == 0 ? 1.0 : 0.0);
-            for (int d = 0; d < 3; ++d) {
-                double k = RL.D[1][0];
-                for (int ax = 0; ax < D; ++ax) k *= RL.proj[ax == d ? 1 : 0][nd[ax]];
-                q.kapb[d] = (d < D) ? k : 0.0;
-            }
-            q.pos[0] = node;
-            q.pos[1] = (D == 3) ? nd[1] + N1 * (nd[0] + N1 * nd[2]) : nd[1] + N1 * nd[0];
-            q.pos[2] = (D == 3) ? nd[2] + N1 * (nd[0] + N1 * nd[1]) : 0;
-            for (int t = 0; t < S::TPL; ++t) {
-                const int g = lane + 64 * t;
+        for (int lane = 0; lane < 64; ++lane)
+            for (int k = 0; k < TPL; ++k) {
+                const int g = lane + 64 * k;
                 const int valid = g < S::NTGT;
                 const int gg = valid ? g : 0;
                 const int z = gg / (MT * NV), rem = gg % (MT * NV), mt = rem / NV, v = rem % NV;
                 const int a = M.a[MS + mt], b = M.b[MS + mt], c = M.c[MS + mt];
                 const int base = z * S::NROWZ * S::RS;
-                q.valid[t] = valid;
-                q.soff[t] = (z * MST + MS + mt) * NV + v;
-                q.off[t][0] = base + v * S::RS + GI.at[a][b][c];
-                q.off[t][1] = base + (NV + v) * S::RS + GI.at[b][a][c];
-                q.off[t][2] = (D == 3) ? base + (2 * NV + v) * S::RS + GI.at[c][a][b] : 0;
-                q.top[t] = base + (S::NFULL + v) * S::RS;
-                q.te[t] = M.e[MS + mt];
-                q.zero[t] = (a + b + c == 0);
+                const int off0 = base + v * S::RS + GI.at[a][b][c];
+                const int off1 = base + (NV + v) * S::RS + GI.at[b][a][c];
+                const int off2 = (D == 3) ? base + (2 * NV + v) * S::RS + GI.at[c][a][b] : 0;
+                const int top = base + (S::NFULL + v) * S::RS;
+                const int soff = (z * MST + MS + mt) * NV + v;
+                t[lane][k][0] = off0 | (off1 << 16);
+                t[lane][k][1] = off2 | (top << 16);
+                t[lane][k][2] = soff | (M.e[MS + mt] << 16) | ((a + b + c == 0) << 20) | (valid << 21);
             }
-        }
     }
+    static_assert(PredShape<D, P>::ZPW * PredShape<D, P>::NROWZ * PredShape<D, P>::RS < (1 << 15),
+                  "row offsets fit 16 bits");
 };
 
 template <int D, int P>
-__constant__ LaneTable<D, P> kLaneTable = LaneTable<D, P>();
+__constant__ TargetTable<D, P> kTargetTable = TargetTable<D, P>();
 
 // L2 projection weight proj[a][i] for a compile-time a and a lane-varying i.
 template <int P>
@@ -616,6 +614,127 @@ __device__ __forceinline__ void project_row_pair(T* row, int emax, int half)
             }
 }
 
+// Per-lane constants of the predictor: the monic Legendre basis at the lane's
+// node along each axis, the node's position in the rows of each derivative
+// axis, the node weight of the folded top flux time mode, and the new-mode
+// targets the lane owns.  Two ways to obtain the same values: read from the
+// compile-time tables (fewer VALU instructions: used by the FP64 instance,
+// which runs at two wavefronts per SIMD) or computed in registers (used by the
+// FP32 instance, measured faster at its four wavefronts per SIMD).
+template <int D, int P, typename T>
+struct LaneSetup {
+    T px[P + 1], py[P + 1], pz[P + 1];
+    int pos[D];
+    T kap[D];
+    Target<D> tg[PredShape<D, P>::TPL];
+};
+
+template <int D, int P, typename T>
+__device__ __forceinline__ void node_position(LaneSetup<D, P, T>& L, int node, int ii, int jj, int kk)
+{
+    constexpr int N1 = P + 1;
+    L.pos[0] = node;
+    if constexpr (D == 3) {
+        L.pos[1] = jj + N1 * (ii + N1 * kk);
+        L.pos[2] = kk + N1 * (ii + N1 * jj);
+    } else {
+        L.pos[1] = jj + N1 * ii;
+    }
+}
+
+template <int D, int P, typename T>
+__device__ __forceinline__ void lane_setup_tables(LaneSetup<D, P, T>& L, int lane, const T* lam)
+{
+    using S = PredShape<D, P>;
+    constexpr int N1 = P + 1;
+    constexpr Rules<P> RL{};
+    const int node = lane % S::NS;
+    const int ii = node % N1, jj = (node / N1) % N1, kk = (D == 3) ? node / (N1 * N1) : 0;
+    const double* nr[3] = {kNodeRows<P>.r[ii], kNodeRows<P>.r[jj], kNodeRows<P>.r[kk]};
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        L.px[a] = T(nr[0][a]);
+        L.py[a] = T(nr[1][a]);
+        L.pz[a] = (D == 3) ? T(nr[2][a]) : T(a == 0 ? 1 : 0);
+    }
+    node_position<D, P, T>(L, node, ii, jj, kk);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double k = RL.D[1][0];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) k *= nr[ax][ax == d ? P + 2 : P + 1];
+        L.kap[d] = lam[d] * T(k);
+    }
+#pragma unroll
+    for (int r = 0; r < S::TPL; ++r) {
+        const int w0 = kTargetTable<D, P>.t[lane][r][0], w1 = kTargetTable<D, P>.t[lane][r][1],
+                  w2 = kTargetTable<D, P>.t[lane][r][2];
+        L.tg[r].off[0] = w0 & 0xFFFF;
+        L.tg[r].off[1] = w0 >> 16;
+        if constexpr (D == 3) L.tg[r].off[2] = w1 & 0xFFFF;
+        L.tg[r].top = w1 >> 16;
+        L.tg[r].soff = w2 & 0xFFFF;
+        L.tg[r].te = (w2 >> 16) & 0xF;
+        L.tg[r].zero = (w2 >> 20) & 1;
+        L.tg[r].valid = (w2 >> 21) & 1;
+    }
+}
+
+template <int D, int P, typename T>
+__device__ __forceinline__ void lane_setup_computed(LaneSetup<D, P, T>& L, int lane, const T* lam)
+{
+    using S = PredShape<D, P>;
+    constexpr int N1 = P + 1, NV = S::NV, MS = S::MS, MST = S::MST, MT = S::MT, RS = S::RS;
+    constexpr Rules<P> RL{};
+    constexpr Modes<D, P> M{};
+    constexpr GIdx<D, P> GI{};
+    const int node = lane % S::NS;
+    const int ii = node % N1, jj = (node / N1) % N1, kk = (D == 3) ? node / (N1 * N1) : 0;
+    const double xn = gl_node(N1, ii), yn = gl_node(N1, jj), zn = gl_node(N1, kk);
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        L.px[a] = T(mleg(a, xn));
+        L.py[a] = T(mleg(a, yn));
+        L.pz[a] = (D == 3) ? T(mleg(a, zn)) : T(a == 0 ? 1 : 0);
+    }
+    node_position<D, P, T>(L, node, ii, jj, kk);
+    const int nd[3] = {ii, jj, kk};
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double k = RL.D[1][0];
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) k *= proj_at<P>(ax == d ? 1 : 0, nd[ax]);
+        L.kap[d] = lam[d] * T(k);
+    }
+#pragma unroll
+    for (int r = 0; r < S::TPL; ++r) {
+        const int t = lane + 64 * r;
+        L.tg[r].valid = t < S::NTGT;
+        const int tt = L.tg[r].valid ? t : 0;
+        const int z = tt / (MT * NV);
+        const int rem = tt % (MT * NV), mt = rem / NV, v = rem % NV;
+        int te = 0, zero = 0, g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+        for (int q = 0; q < MT; ++q)
+            if (q == mt) {
+                const int a = M.a[MS + q], b = M.b[MS + q], c = M.c[MS + q];
+                te = M.e[MS + q];
+                zero = (a + b + c == 0);
+                g0 = GI.at[a][b][c];
+                g1 = GI.at[b][a][c];
+                g2 = (D == 3) ? GI.at[c][a][b] : 0;
+            }
+        L.tg[r].soff = (z * MST + MS + mt) * NV + v;
+        const int base = z * S::NROWZ * RS;
+        L.tg[r].off[0] = base + v * RS + g0;
+        L.tg[r].off[1] = base + (NV + v) * RS + g1;
+        if constexpr (D == 3) L.tg[r].off[2] = base + (2 * NV + v) * RS + g2;
+        L.tg[r].top = base + (S::NFULL + v) * RS;
+        L.tg[r].te = te;
+        L.tg[r].zero = zero;
+    }
+}
+
 template <int D, int P, typename T>
 __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box R,
                                                    StepInfo* __restrict__ info, double gamma, int positivity,
@@ -651,36 +770,15 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
     const int zs = lane / NS;
     const int node = lane % NS;
     const bool active = zs < ZPW;
-    const LaneRec<D, P>& LR = kLaneTable<D, P>.r[lane];
-    T px[P + 1], py[P + 1], pz[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) {
-        px[a] = T(LR.bas[0][a]);
-        py[a] = T(LR.bas[1][a]);
-        pz[a] = T(LR.bas[2][a]);
-    }
-    // position of this lane's node in a row whose derivative axis is d: that
-    // axis fastest, then the other axes in increasing order
-    int pos[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) pos[d] = LR.pos[d];
-    // top flux time mode: weight of axis d in the folded node value,
-    //   lam_d D[1][0] proj[1][n_d] prod_{other axes} proj[0][n_axis]
-    T kap[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) kap[d] = lam[d] * T(LR.kapb[d]);
-    // the new-mode targets this lane accumulates
-    Target<D> tg[S::TPL];
-#pragma unroll
-    for (int r = 0; r < S::TPL; ++r) {
-        tg[r].valid = LR.valid[r];
-        tg[r].soff = LR.soff[r];
-#pragma unroll
-        for (int d = 0; d < D; ++d) tg[r].off[d] = LR.off[r][d];
-        tg[r].top = LR.top[r];
-        tg[r].te = LR.te[r];
-        tg[r].zero = LR.zero[r];
-    }
+    LaneSetup<D, P, T> L;
+    if constexpr (sizeof(T) == 8) lane_setup_tables<D, P, T>(L, lane, lam);
+    else lane_setup_computed<D, P, T>(L, lane, lam);
+    const T(&px)[P + 1] = L.px;
+    const T(&py)[P + 1] = L.py;
+    const T(&pz)[P + 1] = L.pz;
+    const int(&pos)[D] = L.pos;
+    const T(&kap)[D] = L.kap;
+    const Target<D>(&tg)[S::TPL] = L.tg;
     __syncthreads();
 
     // time-independent part of q at this lane's node (the reconstruction)

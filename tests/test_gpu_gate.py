@@ -148,3 +148,61 @@ def test_mlp_training_separates_harvested_labels(hog):
     acc = float(((logits >= 0).float() == y).float().mean())
     print(f"gate training: smooth fraction {frac:.3f}, loss {first:.3f} -> {loss:.3f}, accuracy {acc:.4f}", flush=True)
     assert loss < 0.5 * first and acc > 0.9
+
+
+GATE_FILE = __import__("os").path.join(__import__("os").path.dirname(__file__), "..", "paper_2211_13295_amd",
+                                       "gate_o4_3d.npz")
+
+
+def _run(hog, pb, steps, precision, gate=None):
+    g = hog.Grid.from_problem(pb, 4, precision=precision)
+    frac = []
+    if gate is not None:
+        g.set_gate(gate[0], theta=gate[1])
+    for _ in range(steps):
+        if gate is not None:
+            frac.append(float(g.gate_eval()[1].mean()))
+        g.advance(1)
+    out = (g.get_state(), g.stats()["t"], float(np.mean(frac)) if frac else 0.0)
+    g.close()
+    return out
+
+
+def test_trained_gate_gain_smooth(hog):
+    """What the trained gate buys on smooth flow with a known solution (the
+    isentropic vortex extruded along z, 40^3, fourth order, 10 steps): the
+    share of zones whose WENO applications run with the linear weights (no
+    smoothness indicators, no epsilon division), at the density L1 error
+    against the exact translated vortex of the ungated mixed path."""
+    z = np.load(GATE_FILE)
+    gate = (z["params"], float(z["theta"]))
+    n, steps = 40, 10
+    pb = icgen.vortex3d_perturbed(n=n, seed=2, amp=0.0)
+    err, frac = {}, 0.0
+    for mode in ("fp64", "mixed", "gated"):
+        U, t, f = _run(hog, pb, steps, "fp64" if mode == "fp64" else "mixed", gate if mode == "gated" else None)
+        err[mode] = float(np.abs(U[0] - icgen.vortex_exact_density(n, t)[None]).mean())
+        frac = f if mode == "gated" else frac
+    print(f"gate gain, smooth vortex: {100 * frac:.1f}% of zones on linear weights; density L1 error vs exact "
+          f"{err['gated']:.4e} gated, {err['mixed']:.4e} mixed, {err['fp64']:.4e} FP64", flush=True)
+    assert frac > 0.005
+    assert err["gated"] <= 1.02 * err["mixed"]
+
+
+def test_trained_gate_gain_shocks(hog):
+    """The same on the multi-blast (shocks, 40^3, 8 steps): most of the
+    quiescent ambient runs on linear weights, full WENO stays in the blast
+    zones, and the state stays within the mixed path's shock bound of the FP64
+    path (relative L1)."""
+    z = np.load(GATE_FILE)
+    gate = (z["params"], float(z["theta"]))
+    pb = icgen.multiblast(n=40, seed=3)
+    ref, _, _ = _run(hog, pb, 8, "fp64")
+    Ug, _, frac = _run(hog, pb, 8, "mixed", gate)
+    Um, _, _ = _run(hog, pb, 8, "mixed")
+    rel_g = np.abs(Ug - ref).sum() / np.abs(ref).sum()
+    rel_m = np.abs(Um - ref).sum() / np.abs(ref).sum()
+    print(f"gate gain, multi-blast: {100 * frac:.1f}% of zones on linear weights; rel L1 vs FP64 "
+          f"{rel_g:.3e} gated, {rel_m:.3e} mixed", flush=True)
+    assert frac > 0.5
+    assert rel_g <= 1e-3
