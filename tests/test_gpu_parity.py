@@ -221,6 +221,57 @@ def test_full_size_first_step_sampled(hog):
     np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
 
 
+def _sample_points(n, seed):
+    rng = np.random.default_rng(seed)
+    pts = rng.integers(0, n, size=(48, 3))
+    m = n - 1
+    return np.vstack([pts, [[0, 0, 0], [m, m, m], [0, m, n // 2], [m, 0, 1], [n // 2, n // 2, 0]]])
+
+
+def _full_size_first_step(hog, pb, pts, precision, gate=None):
+    import torch
+    g = grid_for(hog, pb, 4, precision=precision)
+    if gate is not None:
+        g.set_gate(gate[0], theta=gate[1])
+    c = oracle.cfg_from_problem(pb, 4)
+    dto, _ = oracle.cfl_dt(c, pb.U)
+    g.step(dto)
+    U = g.get_state()
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    got = np.stack([U[:, k, j, i] for i, j, k in pts])
+    return got, oracle.step_zones(c, pb.U, dto, pts)
+
+
+@pytest.mark.parametrize("case", ["multiblast_256", "four_quadrant_384"])
+def test_full_size_first_step_sampled_shock_configs(hog, case):
+    """The two shock workloads at their full sizes (multi-blast 256^3, outflow;
+    four-quadrant Riemann problem 384^3), fourth order, first step from the
+    initial state in the benchmark's launch configuration: the FP64 path
+    against the oracle element-wise on sampled zones, and the path these
+    workloads are quoted on (mixed FP32/FP64; for the four-quadrant problem
+    with the trained gate) within the mixed path's shock bound (relative L1
+    over the samples against the FP64 oracle)."""
+    import os
+    if case == "multiblast_256":
+        note("multiblast 256^3 first step, sampled")
+        pb, n, gate = icgen.multiblast(n=256, seed=3), 256, None
+    else:
+        note("four-quadrant 384^3 first step, sampled")
+        pb, n = icgen.four_quadrant(n=384, seed=5), 384
+        z = np.load(os.path.join(os.path.dirname(__file__), "..", "paper_2211_13295_amd", "gate_o4_3d.npz"))
+        gate = (z["params"], float(z["theta"]))
+    pts = _sample_points(n, 1)
+    got, ref = _full_size_first_step(hog, pb, pts, "fp64")
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
+    note(f"{case}: FP64 sampled parity ok")
+    got, ref = _full_size_first_step(hog, pb, pts, "mixed", gate)
+    e = rel_l1(got, ref)
+    note(f"{case}: mixed{' + gate' if gate else ''} sampled relative L1 vs FP64 oracle {e:.3e}")
+    assert e <= 1e-3
+
+
 # ---------------------------------------------------------------- properties
 @pytest.mark.parametrize("ndim,order", CASES)
 def test_conservation_and_free_stream_on_gpu(hog, ndim, order):
