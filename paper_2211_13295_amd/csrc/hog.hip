@@ -173,6 +173,17 @@ struct hog_grid {
 namespace {
 
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+// Thread counts of the marching sweeps (one thread per line, chunk, mode, variable).
+template <int D, int P>
+long long recon_y_threads(const Box& BY)
+{
+    return (long long)BY.n[0] * BY.n[2] * ((BY.n[1] + kRecChunk - 1) / kRecChunk) * (P + 1) * (D + 2);
+}
+template <int P>
+long long recon_z_threads(const Box& R)
+{
+    return (long long)R.n[0] * R.n[1] * ((R.n[2] + kRecChunk - 1) / kRecChunk) * ((P + 1) * (P + 2) / 2) * 5;
+}
 
 hipEvent_t take_event(hog_grid* g)
 {
@@ -244,9 +255,10 @@ int enqueue_step_t(hog_grid* g, double dt_user)
         }
         StageMark m(g, 1);
         k_recon_x<D, P, T><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa, gf, L.I);
-        k_recon_y<D, P, T><<<nblocks(box_size(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa, gf, L.I);
+        k_recon_y<D, P, T><<<nblocks(recon_y_threads<D, P>(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa, gf,
+                                                                                  L.I);
         if constexpr (D == 3)
-            k_recon_z<P, T><<<nblocks(box_size(L.R), 256), 256, 0, s>>>(B, L.BY, L.R, W, g->wa, gf, L.I);
+            k_recon_z<P, T><<<nblocks(recon_z_threads<P>(L.R), 256), 256, 0, s>>>(B, L.BY, L.R, W, g->wa, gf, L.I);
     }
     {
         StageMark m(g, 2);
@@ -744,7 +756,8 @@ static void enqueue_harvest(hog_grid* g, const long long* zones, long long n, fl
     double* A = static_cast<double*>(g->A);
     double* B = static_cast<double*>(g->B);
     k_recon_x<D, P, double><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa, nullptr, L.I);
-    k_recon_y<D, P, double><<<nblocks(box_size(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa, nullptr, L.I);
+    k_recon_y<D, P, double><<<nblocks(recon_y_threads<D, P>(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa,
+                                                                                       nullptr, L.I);
     k_harvest<D, P><<<nblocks(n, 256), 256, 0, s>>>(Uc, L.pad, L.I, A, L.AX, B, L.BY, zones, n, g->wa, feat, maxdev);
 }
 } // extern "C++"

@@ -11,6 +11,7 @@
 //   F[d]  face fluxes [v] over the faces f+1/2, f in [-1, n-1] along d
 // Boxes use interior zone numbering (0..n-1 are interior zones).
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <climits>
 #include "hog_tables.h"
@@ -226,6 +227,56 @@ __global__ __launch_bounds__(256) void k_recon_x(const double* __restrict__ U, P
     }
 }
 
+// The y and z sweeps march along their axis: one thread per (line of zones
+// along the axis, chunk of kRecChunk zones of that line, input mode,
+// variable).  The thread keeps the five values of its stencil in registers,
+// so each input value is read once (plus a four-value halo per chunk), and
+// consecutive threads take consecutive x, so every load and store coalesces.
+constexpr int kRecChunk = 32;
+
+// Calls f(std::integral_constant<int, I>) for I = B .. E-1 (compile-time loop).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// March one line: input values at src[c0 + (o - 2) * stride], outputs for
+// zones c0 .. c0 + (len - 1) * stride of the input box; the output index of
+// the first zone is z0, advancing by zstride.  Writes the centre value to
+// out0 and the WENO coefficients 1..NC to outc[0..NC-1] (NC may be 0).
+template <int P, int NC, typename T, typename G>
+__device__ __forceinline__ void march_line(const T* __restrict__ src, long long c0, long long stride, int len,
+                                           T* __restrict__ out0, T* const* outc, long long z0, long long zstride,
+                                           const WenoArgs& wa0, G&& gate_at)
+{
+    double w[5];
+#pragma unroll
+    for (int o = 0; o < 5; ++o) w[o] = (double)src[c0 + (o - 2) * stride];
+    long long zi = z0;
+    for (int s = 0; s < len; ++s) {
+        out0[zi] = (T)w[2];
+        if constexpr (NC >= 1) {
+            WenoArgs wa = wa0;
+            if (gate_at(s)) wa.linear = 1;
+            T c[P + 1];
+            weno_line<P, T>(w, c, wa);
+#pragma unroll
+            for (int q = 1; q <= NC; ++q) outc[q - 1][zi] = c[q];
+        }
+        if (s + 1 < len) {
+#pragma unroll
+            for (int o = 0; o < 4; ++o) w[o] = w[o + 1];
+            w[4] = (double)src[c0 + (long long)(s + 3) * stride];
+        }
+        zi += zstride;
+    }
+}
+
+// y sweep: A over AX (x-sweep output, P+1 modes) -> B over BY ((a, b) pairs).
 template <int D, int P, typename T>
 __global__ __launch_bounds__(256) void k_recon_y(const T* __restrict__ A, Box AX, Box BY,
                                                  T* __restrict__ B, WenoArgs wa0,
@@ -234,63 +285,74 @@ __global__ __launch_bounds__(256) void k_recon_y(const T* __restrict__ A, Box AX
     constexpr int NV = D + 2;
     constexpr Pairs<P> PR{};
     const long long nA = box_size(AX), nB = box_size(BY);
-    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (z >= nB) return;
-    int i, j, k;
-    box_ijk(BY, z, i, j, k);
-    const WenoArgs wa = gated(wa0, gate, I, i, j, k);
-    const long long c0 = box_index(AX, i, j, k);
-    const long long sy = AX.n[0];
+    const int nx = BY.n[0], nz = BY.n[2], nch = (BY.n[1] + kRecChunk - 1) / kRecChunk;
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)nx * nz * nch * (P + 1) * NV) return;
+    const int ix = (int)(t % nx); t /= nx;
+    const int kz = (int)(t % nz); t /= nz;
+    const int ch = (int)(t % nch); t /= nch;
+    const int v = (int)(t % NV), a = (int)(t / NV);
+    const int i = BY.lo[0] + ix, k = BY.lo[2] + kz, j0 = BY.lo[1] + ch * kRecChunk;
+    const int len = min(kRecChunk, BY.lo[1] + BY.n[1] - j0);
+    const long long c0 = box_index(AX, i, j0, k), z0 = box_index(BY, i, j0, k);
+    auto gate_at = [&](int s) {
+        const int j = j0 + s;
+        return gate && i >= 0 && i < I.n[0] && j >= 0 && j < I.n[1] && k >= 0 && k < I.n[2] &&
+               gate[((long long)k * I.n[1] + j) * I.n[0] + i];
+    };
+    const T* src = A + (long long)(a * NV + v) * nA;
+    // one branch per input mode a: the number of WENO outputs is compile-time
+    static_for<0, P + 1>([&](auto ac) {
+        constexpr int a2 = decltype(ac)::value;
+        if (a != a2) return;
+        T* outc[P];
 #pragma unroll
-    for (int a = 0; a <= P; ++a)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double line[5];
-            T c[P + 1];
-#pragma unroll
-            for (int o = 0; o < 5; ++o) line[o] = (double)A[(a * NV + v) * nA + c0 + (o - 2) * sy];
-            B[(PR.at[a][0] * NV + v) * nB + z] = (T)line[2];
-            if (P - a >= 1) {
-                weno_line<P, T>(line, c, wa);
-#pragma unroll
-                for (int b = 1; b <= P - a; ++b) B[(PR.at[a][b] * NV + v) * nB + z] = c[b];
-            }
-        }
+        for (int b = 1; b <= P - a2; ++b) outc[b - 1] = B + (long long)(PR.at[a2][b] * NV + v) * nB;
+        march_line<P, P - a2, T>(src, c0, AX.n[0], len, B + (long long)(PR.at[a2][0] * NV + v) * nB, outc, z0,
+                                 BY.n[0], wa0, gate_at);
+    });
 }
 
+// z sweep (3D): B over BY -> W over R (spatial modes (a, b, c)).
 template <int P, typename T>
 __global__ __launch_bounds__(256) void k_recon_z(const T* __restrict__ B, Box BY, Box R,
                                                  T* __restrict__ W, WenoArgs wa0,
                                                  const unsigned char* __restrict__ gate, Box I)
 {
     constexpr int NV = 5;
+    constexpr int NPAIR = (P + 1) * (P + 2) / 2;
     constexpr Modes<3, P> M{};
     constexpr Pairs<P> PR{};
     const long long nB = box_size(BY), nR = box_size(R);
-    const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (z >= nR) return;
-    int i, j, k;
-    box_ijk(R, z, i, j, k);
-    const WenoArgs wa = gated(wa0, gate, I, i, j, k);
-    const long long c0 = box_index(BY, i, j, k);
-    const long long sz = (long long)BY.n[0] * BY.n[1];
+    const int nx = R.n[0], ny = R.n[1], nch = (R.n[2] + kRecChunk - 1) / kRecChunk;
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)nx * ny * nch * NPAIR * NV) return;
+    const int ix = (int)(t % nx); t /= nx;
+    const int jy = (int)(t % ny); t /= ny;
+    const int ch = (int)(t % nch); t /= nch;
+    const int v = (int)(t % NV), pi = (int)(t / NV);
+    const int i = R.lo[0] + ix, j = R.lo[1] + jy, k0 = R.lo[2] + ch * kRecChunk;
+    const int len = min(kRecChunk, R.lo[2] + R.n[2] - k0);
+    const long long c0 = box_index(BY, i, j, k0), z0 = box_index(R, i, j, k0);
+    const long long sz = (long long)BY.n[0] * BY.n[1], zs = (long long)R.n[0] * R.n[1];
+    auto gate_at = [&](int s) {
+        const int k = k0 + s;
+        return gate && i >= 0 && i < I.n[0] && j >= 0 && j < I.n[1] && k >= 0 && k < I.n[2] &&
+               gate[((long long)k * I.n[1] + j) * I.n[0] + i];
+    };
+    // one branch per input pair (a, b): the number of WENO outputs is compile-time
+    static_for<0, P + 1>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        static_for<0, P + 1 - b>([&](auto ac) {
+            constexpr int a = decltype(ac)::value;
+            if (pi != PR.at[a][b]) return;
+            T* outc[P];
 #pragma unroll
-    for (int b = 0; b <= P; ++b)
-#pragma unroll
-        for (int a = 0; a + b <= P; ++a)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                double line[5];
-                T c[P + 1];
-#pragma unroll
-                for (int o = 0; o < 5; ++o) line[o] = (double)B[(PR.at[a][b] * NV + v) * nB + c0 + (o - 2) * sz];
-                W[(M.at[a][b][0][0] * NV + v) * nR + z] = (T)line[2];
-                if (P - a - b >= 1) {
-                    weno_line<P, T>(line, c, wa);
-#pragma unroll
-                    for (int cc = 1; cc <= P - a - b; ++cc) W[(M.at[a][b][cc][0] * NV + v) * nR + z] = c[cc];
-                }
-            }
+            for (int cc = 1; cc <= P - a - b; ++cc) outc[cc - 1] = W + (long long)(M.at[a][b][cc][0] * NV + v) * nR;
+            march_line<P, P - a - b, T>(B + (long long)(pi * NV + v) * nB, c0, sz, len,
+                                        W + (long long)(M.at[a][b][0][0] * NV + v) * nR, outc, z0, zs, wa0, gate_at);
+        });
+    });
 }
 
 // ------------------------------------------------------------------------
