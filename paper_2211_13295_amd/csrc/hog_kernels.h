@@ -683,6 +683,84 @@ __device__ __forceinline__ void project_row_pair(T* row, int emax, int half)
 // compile-time tables (fewer VALU instructions: used by the FP64 instance,
 // which runs at two wavefronts per SIMD) or computed in registers (used by the
 // FP32 instance, measured faster at its four wavefronts per SIMD).
+// Value held by lane l ^ 2 within a lane quad (DPP quad_perm 2,3,0,1).
+__device__ __forceinline__ double quad_swap2(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x4E, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x4E, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float quad_swap2(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+}
+
+// project_row in 3D at fourth order by a lane quad: lane q of the quad takes
+// node plane q along the second other axis; the four partial sums are added
+// pairwise ((q0 + q1) + (q2 + q3), the same two numbers in each addition on
+// every lane, so all four lanes hold the same result); the differentiated
+// coefficients go to dst[GIdx(lo, o1, o2)] (all four lanes store the same values).
+template <int P, typename T>
+__device__ __forceinline__ void project_row_quad(const T* row, T* dst, int emax, int q)
+{
+    static_assert(P == 3, "one node plane per lane of the quad");
+    constexpr int N1 = P + 1;
+    constexpr Rules<P> RL{};
+    constexpr GIdx<3, P> GI{};
+    T w[N1];                  // projection weights of this lane's plane
+#pragma unroll
+    for (int o2 = 0; o2 <= P; ++o2) {
+        T v = T(0);
+#pragma unroll
+        for (int k = 0; k < N1; ++k)
+            if (q == k) v = T(RL.proj[o2][k]);
+        w[o2] = v;
+    }
+    T x[N1][N1];              // [o1 node][h]
+#pragma unroll
+    for (int o = 0; o < N1; ++o)
+#pragma unroll
+        for (int h = 0; h < N1; ++h) x[o][h] = row[(q * N1 + o) * N1 + h];
+    T t1[N1][N1];             // [o1 node][hi]
+#pragma unroll
+    for (int o = 0; o < N1; ++o)
+#pragma unroll
+        for (int hi = 1; hi <= P; ++hi) {
+            T s = T(0);
+#pragma unroll
+            for (int h = 0; h < N1; ++h) s += T(RL.proj[hi][h]) * x[o][h];
+            t1[o][hi] = s;
+        }
+    T c[N1][N1][N1];          // [hi][o1][o2], used for hi >= 1, hi + o1 + o2 <= P
+#pragma unroll
+    for (int hi = 1; hi <= P; ++hi)
+#pragma unroll
+        for (int o1 = 0; hi + o1 <= P; ++o1) {
+            T s = T(0);
+#pragma unroll
+            for (int o = 0; o < N1; ++o) s += T(RL.proj[o1][o]) * t1[o][hi];
+#pragma unroll
+            for (int o2 = 0; hi + o1 + o2 <= P; ++o2) {
+                T own = w[o2] * s;
+                own = own + pair_swap(own);
+                own = own + quad_swap2(own);
+                c[hi][o1][o2] = (hi + o1 + o2 > emax) ? T(0) : own;
+            }
+        }
+#pragma unroll
+    for (int o2 = 0; o2 <= P - 1; ++o2)
+#pragma unroll
+        for (int o1 = 0; o1 + o2 <= P - 1; ++o1)
+#pragma unroll
+            for (int lo = 0; lo + o1 + o2 <= P - 1; ++lo) {
+                T s = T(0);
+#pragma unroll
+                for (int hi = lo + 1; hi + o1 + o2 <= P; ++hi)
+                    if (RL.D[hi][lo] != 0.0) s += T(RL.D[hi][lo]) * c[hi][o1][o2];
+                dst[GI.at[lo][o1][o2]] = s;
+            }
+}
+
 template <int D, int P, typename T>
 struct LaneSetup {
     T px[P + 1], py[P + 1], pz[P + 1];
@@ -936,7 +1014,18 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
         //      sums of the folded rows
         {
             const int nfz = nfe * D * NV;
-            if constexpr (D == 3) {
+            if constexpr (D == 3 && P == 3 && sizeof(T) == 8) {
+                static_assert(ZPW == 1 && 2 * NFULL <= 64, "one lane pair per projected row");
+                if (first) {
+                    // 15 rows: one lane quad per row (FP64 only: in FP32 the extra
+                    // registers cost a wavefront per SIMD)
+                    const int r = lane >> 2;
+                    if (r < D * NV) project_row_quad<P, T>(sr + r * RS, sr + r * RS, P, lane & 3);
+                } else {
+                    const int r = lane >> 1;
+                    if (r < nfz) project_row_pair<P, T>(sr + r * RS, P - r / (D * NV), lane & 1);
+                }
+            } else if constexpr (D == 3) {
                 static_assert(2 * ZPW * NFULL <= 64, "one lane pair per projected row");
                 const int s = lane >> 1;
                 if (s < ZPW * nfz) {
