@@ -272,6 +272,39 @@ def test_full_size_first_step_sampled_shock_configs(hog, case):
     assert e <= 1e-3
 
 
+def test_advance_to_an_end_time_matches_oracle(hog):
+    """Device-side time loop with an end time (the last step shortened to land
+    on it) against the oracle's loop: same step count, end time and state."""
+    note("vortex2d 32^2 O3 advance to t_end = 0.7")
+    pb = icgen.vortex2d(n=32)
+    c = oracle.cfg_from_problem(pb, 3)
+    Uo, to, dts = oracle.run(c, pb.U, t_end=0.7)
+    g = grid_for(hog, pb, 3)
+    t = g.advance(100000, t_end=0.7)
+    assert abs(t - to) <= 1e-14 and abs(t - 0.7) <= 1e-14
+    assert rel_l1(g.get_state(), Uo) <= REL_L1
+
+
+@pytest.mark.parametrize("ndim,order,n,bc", [
+    (3, 4, (1, 1, 1), "outflow"), (3, 4, (1, 4, 3), "outflow"), (3, 3, (3, 3, 3), "periodic"),
+    (3, 4, (2, 3, 1), "outflow"), (2, 3, (1, 6, 1), "outflow"), (2, 4, (3, 3, 1), "periodic")])
+def test_degenerate_grids_match_oracle(hog, ndim, order, n, bc):
+    """Grids one to three zones wide (outflow ghosts clamped to a single zone;
+    periodic axes at the minimum of three zones, where every stencil wraps
+    around the whole axis; partial zone groups in the predictor's
+    wavefronts): one step against the oracle.  Periodic axes shorter than
+    three zones are rejected by the library (checked without a device in
+    test_abi)."""
+    note(f"degenerate grid {n} ndim={ndim} order={order} bc={bc}")
+    pb = icgen.random_smooth(n=n, ndim=ndim, seed=sum(n) + order, amp=0.3, bc=bc, h=(0.1, 0.08, 0.11))
+    g = grid_for(hog, pb, order)
+    c = oracle.cfg_from_problem(pb, order)
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    g.step(dt)
+    Uo = oracle.step(c, pb.U, dt)
+    np.testing.assert_allclose(g.get_state(), Uo, rtol=1e-12, atol=1e-13 * np.abs(Uo).max())
+
+
 # ---------------------------------------------------------------- properties
 @pytest.mark.parametrize("ndim,order", CASES)
 def test_conservation_and_free_stream_on_gpu(hog, ndim, order):
