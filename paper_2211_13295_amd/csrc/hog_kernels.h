@@ -426,6 +426,14 @@ __device__ __forceinline__ int xcd_group(int b, int ngroups)
     const int per = (ngroups + kXcds - 1) / kXcds;
     return (b % kXcds) * per + b / kXcds;
 }
+// End (exclusive) of the group range of the XCD that block b runs on.
+__device__ __forceinline__ int xcd_group_end(int b, int ngroups)
+{
+    const int per = (ngroups + kXcds - 1) / kXcds;
+    return min(ngroups, (b % kXcds + 1) * per);
+}
+constexpr int kPrefetchAhead = 256;   // about the wavefronts one XCD keeps resident
+
 inline unsigned xcd_blocks(long long ngroups)
 {
     const long long per = (ngroups + kXcds - 1) / kXcds;
@@ -900,10 +908,20 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
     const T gm1 = T(gamma - 1.0);
     const T lam[3] = {T(info->lam[0]), T(info->lam[1]), T(info->lam[2])};
 
-    for (int t = lane; t < ZPW * MST * NV; t += 64) {
-        const int z = t / (MST * NV), r = t % (MST * NV), m = r / NV, v = r % NV;
-        const long long zone = zbase + z;
-        sq[t] = (m < MS && zone < nR) ? W[(long long)(m * NV + v) * nR + zone] : 0.0;
+    {
+        // all loads first, then the stores, so the round trips overlap
+        constexpr int NL = (ZPW * MST * NV + 63) / 64;
+        T wv[NL];
+#pragma unroll
+        for (int r = 0; r < NL; ++r) {
+            const int t = lane + 64 * r;
+            const int z = t / (MST * NV), rm = t % (MST * NV), m = rm / NV, v = rm % NV;
+            const long long zone = zbase + z;
+            wv[r] = (t < ZPW * MST * NV && m < MS && zone < nR) ? W[(long long)(m * NV + v) * nR + zone] : T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < NL; ++r)
+            if (lane + 64 * r < ZPW * MST * NV) sq[lane + 64 * r] = wv[r];
     }
     if (lane < ZPW) sbad[lane] = 0;
 
@@ -913,6 +931,16 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
     LaneSetup<D, P, T> L;
     if constexpr (sizeof(T) == 8) lane_setup_tables<D, P, T>(L, lane, lam);
     else lane_setup_computed<D, P, T>(L, lane, lam);
+    // L2 warm-up: each wavefront touches the spatial modes of the zone group
+    // kPrefetchAhead groups further on, which a later wavefront of the same
+    // XCD will load (the blocks of one XCD take consecutive groups); the
+    // loaded word is only consumed after the Picard iterations, so nothing waits for it.
+    unsigned pf = 0;
+    if constexpr (sizeof(T) == 8) {
+        asm volatile("" ::: "memory");
+        const long long pz = (long long)min(grp + kPrefetchAhead, xcd_group_end(blockIdx.x, ngroups) - 1) * ZPW;
+        pf = reinterpret_cast<const unsigned*>(W + (long long)(lane < MS * NV ? lane : 0) * nR + pz)[0];
+    }
     const T(&px)[P + 1] = L.px;
     const T(&py)[P + 1] = L.py;
     const T(&pz)[P + 1] = L.pz;
@@ -1091,6 +1119,7 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
         __syncthreads();
     }
 
+    if constexpr (sizeof(T) == 8) asm volatile("" ::"v"(pf));   // long completed; consumed before the stores
     if (Qout) {
         for (int t = lane; t < ZPW * MST * NV; t += 64) {
             const int z = t / (MST * NV), r = t % (MST * NV);
