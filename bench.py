@@ -237,6 +237,71 @@ def mixed_run(hog, torch, pb, order, steps, ref, gate=None):
     return out
 
 
+def shock_workload(hog, torch, name, steps, timed_steps):
+    """Accuracy and throughput of the mixed FP32/FP64 path on a shock workload
+    at full size, against the FP64 path (which matches the FP64 CPU oracle on
+    sampled zones of the same first step in the parity tests).  Both paths take
+    the FP64 run's time steps, so their states compare at the same times; the
+    throughput runs use the device-side time step."""
+    import icgen
+    import numpy as np
+    if name == "multiblast256":
+        pb, label, gate = icgen.multiblast(n=256, seed=3), "multi-blast 256^3 outflow", None
+    else:
+        pb, label = icgen.four_quadrant(n=384, seed=5), "four-quadrant Riemann problem 384^3 outflow"
+        z = np.load(GATE_FILE)
+        gate = (z["params"], float(z["theta"]))
+    order = 4
+    zones = pb.U[0].size
+
+    def timed(precision, with_gate):
+        g = hog.Grid.from_problem(pb, order, precision=precision)
+        if with_gate:
+            g.set_gate(gate[0], theta=gate[1])
+        g.advance(1)
+        g.set_state(pb.U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.advance(timed_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g.close()
+        torch.cuda.empty_cache()
+        return zones * timed_steps / el, el * 1e3 / timed_steps
+
+    def stepped(precision, with_gate, dts=None):
+        g = hog.Grid.from_problem(pb, order, precision=precision)
+        if with_gate:
+            g.set_gate(gate[0], theta=gate[1])
+        out = []
+        dt = g.compute_dt() if dts is None else dts[0]
+        for s in range(steps):
+            if dts is not None:
+                dt = dts[s]
+            out.append(dt)
+            nxt = g.step(dt)
+            dt = nxt
+            if (s + 1) % 25 == 0:
+                print(f"{name} {precision}: step {s + 1}/{steps}", file=sys.stderr, flush=True)
+        U = g.get_state()
+        g.close()
+        torch.cuda.empty_cache()
+        return U, out
+
+    v64, ms64 = timed("fp64", False)
+    vmx, msmx = timed("mixed", gate is not None)
+    ref, dts = stepped("fp64", False)
+    U, _ = stepped("mixed", gate is not None, dts)
+    rel = float(np.abs(U - ref).sum() / np.abs(ref).sum())
+    rho = float(np.abs(U[0] - ref[0]).mean())
+    return {"workload": label, "order": order, "zones": zones, "steps_compared": steps,
+            "fp64": {"value": v64, "unit": UNIT, "ms_per_step": ms64},
+            "mixed" + ("_gated" if gate is not None else ""): {
+                "value": vmx, "unit": UNIT, "ms_per_step": msmx,
+                "rel_l1_vs_fp64": rel, "density_l1_vs_fp64": rho, "t_end": float(sum(dts))},
+            "timed_steps": timed_steps}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +315,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 2 x 1 GiB (known bytes) to "
                          "calibrate the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--shock-workload", choices=["multiblast256", "fourquad384"],
+                    help="instead of the benchmark line: mixed (with the trained gate on the four-quadrant "
+                         "problem) vs FP64 on a full-size shock workload; prints one JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the predictor traffic record from two rocprofv3 counter files and exit")
     args = ap.parse_args()
@@ -269,6 +337,10 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     hog.load()
+    if args.shock_workload:
+        steps = 100 if args.shock_workload == "multiblast256" else 200
+        print(json.dumps(shock_workload(hog, torch, args.shock_workload, steps, 20)), flush=True)
+        return
     if args.copy_calibration:
         x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
