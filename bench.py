@@ -302,6 +302,121 @@ def shock_workload(hog, torch, name, steps, timed_steps):
             "timed_steps": timed_steps}
 
 
+def gate_ablation(hog, torch, name, steps, timed_steps, label_samples=1_000_000):
+    """The gate's speed-up at equal accuracy on a full-size shock workload,
+    mixed FP32/FP64 path, four variants on the same time steps (those of the
+    FP64 run): (A) full WENO, (B) the trained gate, (C) linear weights in
+    every zone, (D) a fresh random selection each step with B's smooth
+    fraction.  Per variant: ms per step (device-side time step), relative L1
+    against the FP64 path, smooth fraction, and for B and D the false-smooth
+    rate against full-WENO labels (weight deviation > 0.25) on sampled zones of
+    the final state.  Also the Amdahl ceiling from the stage times of A."""
+    import icgen
+    import numpy as np
+    pb = icgen.multiblast(n=256, seed=3) if name == "multiblast256" else icgen.four_quadrant(n=384, seed=5)
+    label = "multi-blast 256^3 outflow" if name == "multiblast256" else "four-quadrant Riemann problem 384^3 outflow"
+    z = np.load(GATE_FILE)
+    params, theta = z["params"], float(z["theta"])
+    order, zones = 4, pb.U[0].size
+    rng = np.random.default_rng(7)
+
+    def free(g):
+        g.close()
+        torch.cuda.empty_cache()
+
+    # FP64 reference and its time steps
+    g = hog.Grid.from_problem(pb, order)
+    dts, dt = [], g.compute_dt()
+    for s in range(steps):
+        dts.append(dt)
+        dt = g.step(dt)
+        if (s + 1) % 50 == 0:
+            print(f"ablation {name} fp64: step {s + 1}/{steps}", file=sys.stderr, flush=True)
+    ref = g.get_state()
+    free(g)
+
+    def setup(g, variant, frac):
+        if variant == "B":
+            g.set_gate(params, theta=theta)
+        elif variant == "C":
+            g.set_gate_flags(np.ones(pb.U[0].shape, np.uint8))
+        elif variant == "D":
+            g.set_gate_flags((rng.uniform(size=pb.U[0].shape) < frac).astype(np.uint8))
+
+    out, frac_b, state_b, state_d = {}, 0.0, None, None
+    for variant in ("A", "B", "C", "D"):
+        g = hog.Grid.from_problem(pb, order, precision="mixed")
+        setup(g, variant, frac_b)
+        g.profile(True)
+        t0 = time.perf_counter()
+        try:
+            g.advance(timed_steps)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / timed_steps
+        except hog.HogError as e:
+            ms = None
+            print(f"ablation {name} {variant}: timed run stopped: {e}", file=sys.stderr, flush=True)
+        prof = g.profile_read()
+        g.profile(False)
+        g.set_state(pb.U)
+        fracs, failed = [], None
+        for s in range(steps):
+            if variant == "B" and s % 25 == 0:
+                fracs.append(float(g.gate_eval()[1].mean()))
+            if variant == "D":
+                g.set_gate_flags((rng.uniform(size=pb.U[0].shape) < frac_b).astype(np.uint8))
+            try:
+                g.step(dts[s])
+            except hog.HogError as e:
+                failed = f"step {s + 1}: {e}"
+                break
+            if (s + 1) % 50 == 0:
+                print(f"ablation {name} {variant}: step {s + 1}/{steps}", file=sys.stderr, flush=True)
+        rec = {"ms_per_step": ms, "zone_updates_per_s": zones / ms * 1e3 if ms else None}
+        if failed:
+            rec["failed"] = failed
+        else:
+            U = g.get_state()
+            rec["rel_l1_vs_fp64"] = float(np.abs(U - ref).sum() / np.abs(ref).sum())
+            rec["density_l1_vs_fp64"] = float(np.abs(U[0] - ref[0]).mean())
+            if variant == "B":
+                state_b = U
+            if variant == "D":
+                state_d = U
+        if variant == "A":
+            rec["stages_ms_per_step"] = {k: round(v[0] / timed_steps, 4) for k, v in prof.items()}
+        if variant == "B":
+            frac_b = float(np.mean(fracs))
+            rec["gate_ms_per_step"] = round(prof["gate"][0] / timed_steps, 4)
+        rec["smooth_fraction"] = {"A": 0.0, "B": frac_b, "C": 1.0, "D": frac_b}[variant]
+        out[variant] = rec
+        free(g)
+
+    # false-smooth rates on sampled zones of the final states, labels from full WENO (FP64 weights)
+    sample = np.sort(rng.choice(zones, min(label_samples, zones), replace=False))
+    for variant, U in (("B", state_b), ("D", state_d)):
+        if U is None:
+            continue
+        g = hog.Grid.from_problem(pb, order)
+        g.set_state(U)
+        _, dev = g.harvest(sample)
+        nonsmooth = dev.cpu().numpy() > 0.25
+        if variant == "B":
+            g.set_gate(params, theta=theta)
+            flags = g.gate_eval()[1].reshape(-1)[sample] > 0
+        else:
+            flags = rng.uniform(size=sample.size) < frac_b
+        out[variant]["false_smooth_rate"] = float((flags & nonsmooth).sum() / max(1, nonsmooth.sum()))
+        out[variant]["nonsmooth_fraction_final"] = float(nonsmooth.mean())
+        free(g)
+    a = out["A"]["stages_ms_per_step"]
+    step_ms = sum(a.values())
+    out["amdahl_ceiling"] = {"reconstruction_share": a["reconstruction"] / step_ms,
+                             "speedup_if_reconstruction_were_free": step_ms / (step_ms - a["reconstruction"])}
+    return {"workload": label, "order": order, "zones": zones, "steps_compared": steps, "timed_steps": timed_steps,
+            "path": "mixed FP32/FP64", "gate_theta": theta, "variants": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,6 +433,9 @@ def main():
     ap.add_argument("--shock-workload", choices=["multiblast256", "fourquad384"],
                     help="instead of the benchmark line: mixed (with the trained gate on the four-quadrant "
                          "problem) vs FP64 on a full-size shock workload; prints one JSON line")
+    ap.add_argument("--gate-ablation", choices=["multiblast256", "fourquad384"],
+                    help="instead of the benchmark line: full WENO / trained gate / all linear / random gate "
+                         "on the mixed path of a full-size shock workload; prints one JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the predictor traffic record from two rocprofv3 counter files and exit")
     args = ap.parse_args()
@@ -337,6 +455,10 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     hog.load()
+    if args.gate_ablation:
+        steps = 100 if args.gate_ablation == "multiblast256" else 200
+        print(json.dumps(gate_ablation(hog, torch, args.gate_ablation, steps, 20)), flush=True)
+        return
     if args.shock_workload:
         steps = 100 if args.shock_workload == "multiblast256" else 200
         print(json.dumps(shock_workload(hog, torch, args.shock_workload, steps, 20)), flush=True)

@@ -199,8 +199,17 @@ int hog_set_gate(hog_grid* g, const float* params, double theta);
 
 /* Evaluate the gate on the current state: host arrays of nx*ny*nz logits
  * and/or flags (either may be NULL).  Synchronises.
- * Errors: HOG_ESTATE (no gate or no state), HOG_EDEVICE. */
+ * Errors: HOG_ESTATE (no network, fixed flags set, or no state), HOG_EDEVICE. */
 int hog_gate_eval(hog_grid* g, float* logits, unsigned char* flags);
+
+/* Use fixed per-zone flags (host array of nx*ny*nz bytes, x fastest, each
+ * 0 or 1; copied) in every later step instead of the network's, with the
+ * same effect (flag 1: the 1D applications centred at that zone use the
+ * linear weights).  For ablations of the gate: all zones linear, or a
+ * random selection of the network's smooth fraction.  flags = NULL returns
+ * to the network loaded by hog_set_gate, or to no gate; hog_set_gate also
+ * clears fixed flags.  Synchronises.  Errors: HOG_EINVAL (a flag not 0/1). */
+int hog_set_gate_flags(hog_grid* g, const unsigned char* flags);
 
 /* Training samples from the current state (FP64 path only): for the n
  * interior zone indices in zones (device array, x fastest) write the features

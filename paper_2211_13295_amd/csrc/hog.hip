@@ -159,8 +159,10 @@ struct hog_grid {
     double* U[2];
     void *A, *B, *W, *FP, *Q;     // element type: double (FP64) or float (mixed)
     double *F[3], *stage;
-    // learned gate (device copy of the parameters, per-zone flags and logits)
-    bool gate_on;
+    // learned gate (device copy of the parameters, per-zone flags and logits);
+    // gate_on: flags are used by the steps; gate_fixed: they were set by the
+    // caller (no inference); gate_net: a network is loaded
+    bool gate_on, gate_fixed, gate_net;
     void* gate;
     unsigned char* flags;
     float* logits;
@@ -247,12 +249,12 @@ int enqueue_step_t(hog_grid* g, double dt_user)
     }
     {
         const unsigned char* gf = nullptr;
-        if (g->gate_on) {
+        if (g->gate_on && !g->gate_fixed) {
             StageMark mg(g, 5);
             k_gate_infer<D><<<nblocks(box_size(L.I), 16), 64, 0, s>>>(
                 Uc, L.pad, L.I, static_cast<const GateParams<D>*>(g->gate), g->flags, nullptr);
-            gf = g->flags;
         }
+        if (g->gate_on) gf = g->flags;
         StageMark m(g, 1);
         k_recon_x<D, P, T><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa, gf, L.I);
         k_recon_y<D, P, T><<<nblocks(recon_y_threads<D, P>(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa, gf,
@@ -398,7 +400,7 @@ int hog_create(const hog_config* cfg, void* workspace, size_t bytes, void* hip_s
     for (int d = 0; d < 3; ++d) g->F[d] = (d < P.nd) ? reinterpret_cast<double*>(g->ws + P.off_F[d]) : nullptr;
     g->Q = cfg->debug ? static_cast<void*>(g->ws + P.off_Q) : nullptr;
     g->stage = reinterpret_cast<double*>(g->ws + P.off_stage);
-    g->gate_on = false;
+    g->gate_on = g->gate_fixed = g->gate_net = false;
     g->gate = g->ws + P.off_gate;
     g->flags = reinterpret_cast<unsigned char*>(g->ws + P.off_flags);
     g->logits = reinterpret_cast<float*>(g->ws + P.off_logits);
@@ -702,11 +704,29 @@ static int set_gate_t(hog_grid* g, const float* prm, double theta)
 int hog_set_gate(hog_grid* g, const float* params, double theta)
 {
     if (!g) return fail(HOG_EINVAL, "NULL handle");
-    if (!params) { g->gate_on = false; return HOG_OK; }
+    g->gate_fixed = false;
+    if (!params) { g->gate_on = g->gate_net = false; return HOG_OK; }
     if (!(theta > 0.0 && theta < 1.0)) return fail(HOG_EINVAL, "theta must be in (0, 1)");
     const int rc = (g->P.nd == 3) ? set_gate_t<3>(g, params, theta) : set_gate_t<2>(g, params, theta);
-    if (rc) return rc;
-    g->gate_on = true;
+    if (rc) { g->gate_on = g->gate_net = false; return rc; }
+    g->gate_on = g->gate_net = true;
+    return HOG_OK;
+}
+
+int hog_set_gate_flags(hog_grid* g, const unsigned char* flags)
+{
+    if (!g) return fail(HOG_EINVAL, "NULL handle");
+    if (!flags) {
+        g->gate_fixed = false;
+        g->gate_on = g->gate_net;
+        return HOG_OK;
+    }
+    const long long N = box_size(g->P.I);
+    for (long long i = 0; i < N; ++i)
+        if (flags[i] > 1) return fail(HOG_EINVAL, "flags must be 0 or 1 (zone %lld)", i);
+    HIP_TRY(hipMemcpyAsync(g->flags, flags, N, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->gate_fixed = g->gate_on = true;
     return HOG_OK;
 }
 
@@ -725,7 +745,8 @@ static void enqueue_ghost(hog_grid* g)
 int hog_gate_eval(hog_grid* g, float* logits, unsigned char* flags)
 {
     if (!g) return fail(HOG_EINVAL, "NULL handle");
-    if (!g->gate_on) return fail(HOG_ESTATE, "no gate set");
+    if (!g->gate_net) return fail(HOG_ESTATE, "no gate network set");
+    if (g->gate_fixed) return fail(HOG_ESTATE, "fixed gate flags are set");
     if (!g->have_state) return fail(HOG_ESTATE, "no state set");
     const Plan& L = g->P;
     const long long N = box_size(L.I);

@@ -73,6 +73,7 @@ def load():
     L.hog_gate_param_count.argtypes = [C.c_int, ip_]
     L.hog_set_gate.argtypes = [vp, vp, C.c_double]
     L.hog_gate_eval.argtypes = [vp, vp, vp]
+    L.hog_set_gate_flags.argtypes = [vp, vp]
     L.hog_harvest.argtypes = [vp, vp, C.c_longlong, vp, vp]
     L.hog_mlp_workspace_size.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_size_t)]
     L.hog_mlp_create.argtypes = [C.c_int, C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)]
@@ -82,7 +83,8 @@ def load():
     L.hog_mlp_grads.argtypes = [vp, vp, vp, vp, C.c_int, vp, vp]
     L.hog_mlp_step.argtypes = [vp, vp, vp, vp, C.c_int, C.c_float, vp]
     L.hog_mlp_predict.argtypes = [vp, vp, C.c_int, vp]
-    for f in ("hog_gate_param_count", "hog_set_gate", "hog_gate_eval", "hog_harvest", "hog_mlp_workspace_size",
+    for f in ("hog_gate_param_count", "hog_set_gate", "hog_gate_eval", "hog_set_gate_flags", "hog_harvest",
+              "hog_mlp_workspace_size",
               "hog_mlp_create", "hog_mlp_destroy", "hog_mlp_set_params", "hog_mlp_get_params", "hog_mlp_grads",
               "hog_mlp_step", "hog_mlp_predict"):
         getattr(L, f).restype = C.c_int
@@ -166,9 +168,12 @@ class Grid:
         return g
 
     def close(self):
+        """Destroy the handle and drop the workspace (its device memory goes back
+        to torch's allocator once nothing else references it)."""
         if getattr(self, "_h", None) is not None and self._h.value:
             load().hog_destroy(self._h)
             self._h = C.c_void_p()
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -255,6 +260,16 @@ class Grid:
         v = np.ascontiguousarray(params, dtype=np.float32)
         assert v.size == param_count(self.ndim)
         _check(load().hog_set_gate(self._h, v.ctypes.data_as(C.c_void_p), float(theta)))
+
+    def set_gate_flags(self, flags):
+        """Fixed per-zone flags (array of the state's zone shape, 0/1) used by
+        later steps instead of the network; None returns to the network."""
+        if flags is None:
+            _check(load().hog_set_gate_flags(self._h, None))
+            return
+        f = np.ascontiguousarray(flags, dtype=np.uint8).reshape(-1)
+        assert f.size == self.nzones
+        _check(load().hog_set_gate_flags(self._h, f.ctypes.data_as(C.c_void_p)))
 
     def gate_eval(self):
         n = self.nzones

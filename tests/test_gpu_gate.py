@@ -102,6 +102,32 @@ def test_gated_step_matches_oracle(hog, ndim, order):
     assert np.abs(Uo - oracle.step(c, pb.U, dt)).max() > 1e-10
 
 
+@pytest.mark.parametrize("ndim,order", [(2, 4), (3, 4), (3, 3)])
+def test_fixed_gate_flags_step_matches_oracle(hog, ndim, order):
+    """Caller-set flags (a seeded random selection, as in the gate ablations)
+    give the oracle's gated step for the same flags."""
+    n = (16, 14, 12) if ndim == 3 else (40, 36, 1)
+    pb = icgen.random_smooth(n=n, ndim=ndim, seed=20 + order, amp=0.3)
+    flags = (np.random.default_rng(ndim + order).uniform(size=pb.U[0].shape) < 0.4).astype(np.uint8)
+    c = oracle.cfg_from_problem(pb, order)
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    g = hog.Grid.from_problem(pb, order)
+    g.set_gate_flags(flags)
+    g.step(dt)
+    Uo, _ = oracle.step_gated(c, pb.U, dt, flags)
+    assert np.abs(g.get_state() - Uo).sum() / np.abs(Uo).sum() <= 1e-12
+    with pytest.raises(hog.HogError):
+        g.gate_eval()                                   # no network, fixed flags
+    bad = flags.copy()
+    bad.flat[3] = 2
+    with pytest.raises(hog.HogError):
+        g.set_gate_flags(bad)
+    g.set_gate_flags(None)                              # back to no gate: the plain step
+    g.set_state(pb.U)
+    g.step(dt)
+    assert np.abs(g.get_state() - oracle.step(c, pb.U, dt)).sum() / np.abs(Uo).sum() <= 1e-12
+
+
 def test_mlp_gradients_match_cpu(hog):
     rng = np.random.default_rng(1)
     nf, B = 65, 256
