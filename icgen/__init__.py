@@ -285,3 +285,22 @@ def random_smooth(n=(8, 8, 8), ndim=3, seed=0, amp=0.05, gamma=1.4, h=(0.1, 0.1,
     nn = (n[0], n[1], n[2] if ndim == 3 else 1)
     return Problem(U=U, ndim=ndim, n=nn, h=tuple(h), origin=(0.0, 0.0, 0.0),
                    bc=(bc,) * 3, gamma=gamma, meta=dict(name="random_smooth", seed=seed))
+
+
+def cold_wave(n=32, ndim=2, amp=2.0, p0=1e-3, gamma=1.4, axis=0):
+    """Cold flow on the periodic unit box: rho = 1, pressure p0 (small), and a
+    velocity sin wave u_axis = amp * sin(2 pi x_axis) along one axis.  Kinetic
+    energy dominates, so limited slopes of the conserved variables easily give
+    negative face pressures: the case for the positivity fallback."""
+    shape = (n,) * ndim
+    h = 1.0 / n
+    coord = _centres(n, h, 0.0)
+    sl = [None] * ndim
+    sl[ndim - 1 - axis] = slice(None)
+    u = amp * np.sin(2.0 * math.pi * coord)[tuple(sl)] * np.ones(shape)
+    vel = [np.zeros(shape) for _ in range(ndim)]
+    vel[axis] = u
+    U = prim_to_cons(np.ones(shape), vel, p0 * np.ones(shape), gamma)
+    nn = (n, n, n if ndim == 3 else 1)
+    return Problem(U=U, ndim=ndim, n=nn, h=(h, h, h), origin=(0.0, 0.0, 0.0),
+                   bc=("periodic",) * 3, gamma=gamma, meta=dict(name="cold_wave", amp=amp, p0=p0))

@@ -95,6 +95,8 @@ def lib():
             getattr(L, f).argtypes = [C.c_int, C.c_int]
             getattr(L, f).restype = C.c_double
         L.oracle_gauss.argtypes = [C.c_int, dp, dp]
+        L.oracle_mc.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.oracle_mc.restype = C.c_double
         _lib = L
     return _lib
 
@@ -274,6 +276,11 @@ def phys_flux(cfg, d, U):
     out = np.zeros(cfg.ndim + 2)
     lib().oracle_phys_flux(C.byref(cfg), d, _state(U), out)
     return out
+
+
+def mc(a, b, cfac):
+    """Limited undivided slope of the second-order scheme (Fig. 3)."""
+    return lib().oracle_mc(float(a), float(b), float(cfac))
 
 
 def gauss(n):

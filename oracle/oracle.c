@@ -18,7 +18,8 @@
  *       Fig. 7 Update_U_Timestep),
  *   (6) the CFL time step of the new state with a min over zones (Fig. 7).
  * The paper prints the scheme only at second order with the predictor and
- * Riemann solver left empty; the third/fourth order formulas here are the
+ * Riemann solver left empty; the second-order path follows Figs. 3-7 with the
+ * pointwise predictor read as a Hancock step; the third/fourth order formulas here are the
  * readings stated in the design notes (successive x->y->z WENO sweeps with
  * L/C/R quadratic candidates at O3 and a WENO-AO combination at O4, a Picard
  * predictor with tensor Gauss-Legendre L2 projection, 2-point Gauss face
@@ -47,7 +48,7 @@
 typedef struct {
     int ndim;          /* 2 or 3 */
     int nx, ny, nz;    /* interior zones; nz = 1 in 2D */
-    int order;         /* 3 or 4: polynomial degree p = order - 1 */
+    int order;         /* 2 (the scheme of Figs. 3-7), 3 or 4: polynomial degree p = order - 1 */
     int riemann;       /* 0 HLLC, 1 HLL, 2 Rusanov */
     int bc[3];         /* per axis: 0 periodic, 1 outflow (zero gradient) */
     int linear_weno;   /* 1: nonlinear weights replaced by the linear ones */
@@ -682,6 +683,207 @@ static void face_flux(const ocfg *c, int dir, const double *qa, const double *qb
 }
 
 /* ------------------------------------------------------------------------ */
+/* Second-order scheme (Sec. II.1, Figs. 3-7)                                */
+/* ------------------------------------------------------------------------ */
+/* Monotonised-central limiter with a compression factor (Fig. 3): the
+ * limited undivided slope from the forward difference a and the backward
+ * difference b.  Fortran's SIGN(0.5, x) is +0.5 at x = 0; the result is 0
+ * whenever a and b differ in sign or either is 0. */
+double oracle_mc(double a, double b, double cfac)
+{
+    double m = fmin(0.5 * fabs(a + b), fmin(cfac * fabs(a), cfac * fabs(b)));
+    double sa = (a >= 0.0) ? 0.5 : -0.5;
+    double sb = (b >= 0.0) ? 0.5 : -0.5;
+    return m * (sa + sb);
+}
+
+/* Compression factor of Fig. 3: 2 for the density, 1.5 for the others. */
+static double o2_cfac(int v) { return v == 0 ? 2.0 : 1.5; }
+
+/* Modes of zone (i, j, k) at second order, stored in the space-time mode
+ * order of st_modes(nd, 1): q[0..nv) the zone mean (mode 1 of Fig. 3),
+ * q[(1+d)*nv ..] the limited undivided slope along axis d (modes 2-4, Fig. 3),
+ * q[(1+nd)*nv ..] the time mode, dt times the time rate of change (mode 5,
+ * Fig. 4).  The paper leaves the body of the pointwise predictor empty; it is
+ * read as the Hancock step of MUSCL-Hancock in conserved variables: the time
+ * mode is minus the sum over the axes of dt/dx_d times the difference of the
+ * physical flux between the zone's two face-centre values U +- S_d/2.
+ * With the positivity option, a zone where one of those face-centre values or
+ * one of the face states U +- S_d/2 + U5/2 of Fig. 5 is inadmissible falls
+ * back to its mean (zero slopes, zero time mode).  Returns 1 for such a zone. */
+static int o2_zone(const ocfg *c, const grid_t *g, const double *P, const double *lam, int i, int j, int k,
+                   double *q)
+{
+    int nd = g->nd, nv = g->nv;
+    double *U5 = q + (1 + nd) * nv;
+    for (int v = 0; v < nv; ++v) {
+        q[v] = P[v * g->vs + pidx(g, i, j, k)];
+        U5[v] = 0.0;
+    }
+    int bad = 0;
+    for (int d = 0; d < nd; ++d) {
+        int o[3] = {0, 0, 0};
+        o[d] = 1;
+        double *S = q + (1 + d) * nv;
+        double Um[MAXV], Up[MAXV], Fm[MAXV], Fp[MAXV];
+        for (int v = 0; v < nv; ++v) {
+            double lo = P[v * g->vs + pidx(g, i - o[0], j - o[1], k - o[2])];
+            double hi = P[v * g->vs + pidx(g, i + o[0], j + o[1], k + o[2])];
+            S[v] = oracle_mc(hi - q[v], q[v] - lo, o2_cfac(v));
+            Um[v] = q[v] - 0.5 * S[v];
+            Up[v] = q[v] + 0.5 * S[v];
+        }
+        if (!admissible(c, Um) || !admissible(c, Up)) bad = 1;
+        phys_flux(c, d, Um, Fm);
+        phys_flux(c, d, Up, Fp);
+        for (int v = 0; v < nv; ++v) U5[v] -= lam[d] * (Fp[v] - Fm[v]);
+    }
+    for (int d = 0; d < nd && !bad; ++d)
+        for (int side = 0; side < 2 && !bad; ++side) {
+            double W[MAXV];
+            for (int v = 0; v < nv; ++v)
+                W[v] = q[v] + (side ? 0.5 : -0.5) * q[(1 + d) * nv + v] + 0.5 * U5[v];
+            if (!admissible(c, W)) bad = 1;
+        }
+    if (!c->positivity || !bad) return 0;
+    for (int t = nv; t < (2 + nd) * nv; ++t) q[t] = 0.0;
+    return 1;
+}
+
+/* Face flux of Fig. 5 between zone qa (lower index) and qb along dir: the
+ * Riemann solver at the face centre and half time step, with the states
+ * U + S/2 + U5/2 from qa and U - S/2 + U5/2 from qb. */
+static void o2_face_flux(const ocfg *c, int dir, const double *qa, const double *qb, double *F)
+{
+    int nd = c->ndim, nv = nd + 2;
+    double UL[MAXV], UR[MAXV];
+    for (int v = 0; v < nv; ++v) {
+        UL[v] = qa[v] + 0.5 * qa[(1 + dir) * nv + v] + 0.5 * qa[(1 + nd) * nv + v];
+        UR[v] = qb[v] - 0.5 * qb[(1 + dir) * nv + v] + 0.5 * qb[(1 + nd) * nv + v];
+    }
+    oracle_riemann(c, dir, UL, UR, F);
+}
+
+/* Increment of Fig. 6 for one zone: -dt (F_d(+) - F_d(-)) / dx_d summed over
+ * the axes, then added to the zone mean (Fig. 7). */
+static void o2_update(int nd, const double *u, double dt, const double *h, double (*Fm)[MAXV],
+                      double (*Fp)[MAXV], double *out)
+{
+    int nv = nd + 2;
+    for (int v = 0; v < nv; ++v) {
+        double du = 0.0;
+        for (int d = 0; d < nd; ++d) du -= dt * (Fp[d][v] - Fm[d][v]) / h[d];
+        out[v] = u[v] + du;
+    }
+}
+
+/* One second-order step of the whole grid, in the stage order of Fig. 1:
+ * ghost zones, limiter (Fig. 3) and predictor (Fig. 4) on the interior grown
+ * by one zone per active axis, face fluxes (Fig. 5), update (Figs. 6-7).
+ * Same arguments as oracle_step_count. */
+static int o2_step(const ocfg *c, const double *U, double dt, double *Unew, long long *ntroubled)
+{
+    grid_t g;
+    grid_init(c, &g);
+    int nd = g.nd, nv = g.nv;
+    double h[3] = {c->dx, c->dy, c->dz};
+    double lam[3] = {dt / h[0], dt / h[1], dt / h[2]};
+    double *P = make_padded(c, &g, U);
+    if (!P) return -1;
+    int e[3] = {g.n[0] + 2, g.n[1] + 2, (nd == 3) ? g.n[2] + 2 : 1};
+    size_t ne = (size_t)e[0] * e[1] * e[2];
+    size_t qs = (size_t)(2 + nd) * nv;
+    double *Q = (double *)malloc(sizeof(double) * ne * qs);
+    if (!Q) { free(P); return -1; }
+    int o3 = (nd == 3) ? 1 : 0;
+    long long nbad = 0;
+#pragma omp parallel for schedule(static) collapse(2) reduction(+ : nbad)
+    for (int k = 0; k < e[2]; ++k)
+        for (int j = 0; j < e[1]; ++j)
+            for (int i = 0; i < e[0]; ++i)
+                nbad += o2_zone(c, &g, P, lam, i - 1, j - 1, k - o3, Q + (((size_t)k * e[1] + j) * e[0] + i) * qs);
+    *ntroubled = nbad;
+#define QAT(i, j, k) (Q + (((size_t)((k) + o3) * e[1] + ((j) + 1)) * e[0] + ((i) + 1)) * qs)
+    size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+#pragma omp parallel for schedule(static) collapse(2)
+    for (int k = 0; k < g.n[2]; ++k)
+        for (int j = 0; j < g.n[1]; ++j)
+            for (int i = 0; i < g.n[0]; ++i) {
+                double Fm[3][MAXV], Fp[3][MAXV], u[MAXV], un[MAXV] = {0};
+                for (int d = 0; d < nd; ++d) {
+                    int o[3] = {0, 0, 0};
+                    o[d] = 1;
+                    o2_face_flux(c, d, QAT(i - o[0], j - o[1], k - o[2]), QAT(i, j, k), Fm[d]);
+                    o2_face_flux(c, d, QAT(i, j, k), QAT(i + o[0], j + o[1], k + o[2]), Fp[d]);
+                }
+                size_t z = ((size_t)k * g.n[1] + j) * g.n[0] + i;
+                for (int v = 0; v < nv; ++v) u[v] = U[v * N + z];
+                o2_update(nd, u, dt, h, Fm, Fp, un);
+                for (int v = 0; v < nv; ++v) Unew[v * N + z] = un[v];
+            }
+#undef QAT
+    free(Q);
+    free(P);
+    return 0;
+}
+
+/* Second-order update of a list of zones, each recomputed from scratch. */
+static int o2_step_zones(const ocfg *c, const double *U, double dt, int nlist, const int *ijk, double *out)
+{
+    grid_t g;
+    grid_init(c, &g);
+    int nd = g.nd, nv = g.nv;
+    double h[3] = {c->dx, c->dy, c->dz};
+    double lam[3] = {dt / h[0], dt / h[1], dt / h[2]};
+    double *P = make_padded(c, &g, U);
+    if (!P) return -1;
+    size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+#pragma omp parallel for schedule(static)
+    for (int s = 0; s < nlist; ++s) {
+        int i = ijk[3 * s], j = ijk[3 * s + 1], k = (nd == 3) ? ijk[3 * s + 2] : 0;
+        double qc[5 * MAXV], qm[5 * MAXV], qp[5 * MAXV];
+        double Fm[3][MAXV], Fp[3][MAXV], u[MAXV];
+        o2_zone(c, &g, P, lam, i, j, k, qc);
+        for (int d = 0; d < nd; ++d) {
+            int o[3] = {0, 0, 0};
+            o[d] = 1;
+            o2_zone(c, &g, P, lam, i - o[0], j - o[1], k - o[2], qm);
+            o2_zone(c, &g, P, lam, i + o[0], j + o[1], k + o[2], qp);
+            o2_face_flux(c, d, qm, qc, Fm[d]);
+            o2_face_flux(c, d, qc, qp, Fp[d]);
+        }
+        size_t z = ((size_t)k * g.n[1] + j) * g.n[0] + i;
+        for (int v = 0; v < nv; ++v) u[v] = U[v * N + z];
+        o2_update(nd, u, dt, h, Fm, Fp, out + (size_t)s * nv);
+    }
+    free(P);
+    return 0;
+}
+
+/* Second-order stage taps: W [zone][1+nd][nv] (mean and limited slopes) and
+ * q [zone][2+nd][nv] (with the time mode) of every interior zone. */
+static int o2_stage_modes(const ocfg *c, const double *U, double dt, double *Wout, double *qout)
+{
+    grid_t g;
+    grid_init(c, &g);
+    int nd = g.nd, nv = g.nv;
+    double h[3] = {c->dx, c->dy, c->dz};
+    double lam[3] = {dt / h[0], dt / h[1], dt / h[2]};
+    double *P = make_padded(c, &g, U);
+    if (!P) return -1;
+    size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+    for (size_t z = 0; z < N; ++z) {
+        int i = (int)(z % g.n[0]), j = (int)((z / g.n[0]) % g.n[1]), k = (int)(z / ((size_t)g.n[0] * g.n[1]));
+        double q[5 * MAXV];
+        o2_zone(c, &g, P, lam, i, j, k, q);
+        if (Wout) memcpy(Wout + z * (1 + nd) * nv, q, sizeof(double) * (1 + nd) * nv);
+        if (qout) memcpy(qout + z * (2 + nd) * nv, q, sizeof(double) * (2 + nd) * nv);
+    }
+    free(P);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Public entry points                                                       */
 /* ------------------------------------------------------------------------ */
 /* CFL time step of a state (interior SoA): dt = cfl / max_zones sum_d
@@ -728,6 +930,7 @@ int oracle_step_count(const ocfg *c, const double *U, double dt, double *Unew, l
 int oracle_step_gated(const ocfg *c, const double *U, double dt, const unsigned char *gate, double *Unew,
                       long long *ntroubled)
 {
+    if (c->order == 2) return gate ? -2 : o2_step(c, U, dt, Unew, ntroubled);
     grid_t g;
     grid_init(c, &g);
     int nd = g.nd, nv = g.nv, p = c->order - 1;
@@ -783,6 +986,7 @@ int oracle_step_gated(const ocfg *c, const double *U, double dt, const unsigned 
  * spot checks of large grids).  ijk: nlist triples; out: [nlist][nv]. */
 int oracle_step_zones(const ocfg *c, const double *U, double dt, int nlist, const int *ijk, double *out)
 {
+    if (c->order == 2) return o2_step_zones(c, U, dt, nlist, ijk, out);
     grid_t g;
     grid_init(c, &g);
     int nd = g.nd, nv = g.nv, p = c->order - 1;
@@ -853,6 +1057,7 @@ int oracle_run(const ocfg *c, double *U, int nsteps, double t_end, double *t_out
  * modes q [zone][nst][nv] of every interior zone (ignoring zones beyond). */
 int oracle_stage_modes(const ocfg *c, const double *U, double dt, double *Wout, double *qout)
 {
+    if (c->order == 2) return o2_stage_modes(c, U, dt, Wout, qout);
     grid_t g;
     grid_init(c, &g);
     int nd = g.nd, nv = g.nv, p = c->order - 1;
@@ -885,6 +1090,7 @@ int oracle_stage_modes(const ocfg *c, const double *U, double dt, double *Wout, 
  * 1D applications centred at the zone (full nonlinear weights). */
 int oracle_zone_maxdev(const ocfg *c, const double *U, double *out)
 {
+    if (c->order == 2) return -2;   /* no WENO weights at second order */
     grid_t g;
     grid_init(c, &g);
     double *P = make_padded(c, &g, U);

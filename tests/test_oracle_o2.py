@@ -1,0 +1,295 @@
+"""Pins of the oracle's second-order scheme (Sec. II.1, Figs. 3-7): the MC
+limiter against its ratio form, the Hancock predictor against the exact time
+derivative of linear advection, the reduction to the first-order Godunov
+scheme where every slope is limited away, conservation, symmetry, the Sod
+problem against its exact solution and the design order on the vortex
+(Table XII's second-order row)."""
+import math
+
+import numpy as np
+import pytest
+
+import icgen
+import oracle
+from tests.exact_riemann import zone_average_density
+from tests.test_oracle_scheme import _golden_orders
+
+
+def mc_ratio_form(a, b, cfac):
+    """MC limiter in the slope-ratio form of Sweby's diagram: s = a * phi(b/a)
+    with phi(r) = max(0, min(cfac r, (1 + r)/2, cfac)); cfac = 2 is van Leer's
+    monotonised-central limiter."""
+    if a == 0.0:
+        return 0.0
+    r = b / a
+    return a * max(0.0, min(cfac * r, 0.5 * (1.0 + r), cfac))
+
+
+@pytest.mark.parametrize("cfac", [1.5, 2.0, 1.0])
+def test_mc_matches_the_ratio_form(cfac):
+    rng = np.random.default_rng(7)
+    for _ in range(2000):
+        a, b = rng.normal(size=2) * 10.0 ** rng.integers(-3, 3, size=2)
+        assert oracle.mc(a, b, cfac) == pytest.approx(mc_ratio_form(a, b, cfac), rel=1e-14, abs=1e-300)
+
+
+def test_mc_limits():
+    for cfac in (1.5, 2.0):
+        assert oracle.mc(0.3, 0.3, cfac) == 0.3           # linear data is left alone
+        assert oracle.mc(-0.7, -0.7, cfac) == -0.7
+        assert oracle.mc(0.3, -0.2, cfac) == 0.0          # extremum: flat
+        assert oracle.mc(0.0, 5.0, cfac) == 0.0
+        assert oracle.mc(5.0, 0.0, cfac) == 0.0
+        assert oracle.mc(1.0, 10.0, cfac) == cfac         # steep side capped at cfac * the gentle one
+        assert oracle.mc(10.0, 1.0, cfac) == cfac
+        assert oracle.mc(1.0, 2.0, cfac) == pytest.approx(min(1.5, cfac))   # central difference when it fits
+    rng = np.random.default_rng(3)
+    for _ in range(500):
+        a, b = rng.normal(size=2)
+        s = oracle.mc(a, b, 2.0)
+        assert s == oracle.mc(b, a, 2.0)
+        assert abs(s) <= 2.0 * min(abs(a), abs(b)) + 1e-15
+        assert s * a >= 0.0 and s * b >= 0.0
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_compression_factor_is_two_for_density_and_one_and_a_half_otherwise(ndim):
+    """Zone whose forward difference is 4x its backward one in every conserved
+    variable (density profile 1, 1.01, 1.05 along x, constant velocity and
+    pressure): the MC slope is cfac times the backward difference, so the
+    density slope is 2x and the momentum / energy slopes 1.5x (Fig. 3)."""
+    n = 5
+    shape = (n,) * ndim
+    prof = np.array([1.0, 1.0, 1.01, 1.05, 1.05])
+    rho = np.broadcast_to(prof, shape).copy()
+    vel = (0.5, -0.4, 0.3)[:ndim]
+    U = icgen.prim_to_cons(rho, [np.full(shape, v) for v in vel], np.full(shape, 0.9), 1.4)
+    c = oracle.make_cfg(ndim, (n, n, n), 2, (0.1, 0.1, 0.1), bc=("outflow",) * 3)
+    W, _ = oracle.stage_modes(c, U, 1e-3, want_q=False)
+    z = 2 + n * (2 + (n * 2 if ndim == 3 else 0))      # x = 2 on an inner row
+    back = U[(slice(None),) + (2,) * (ndim - 1) + (2,)] - U[(slice(None),) + (2,) * (ndim - 1) + (1,)]
+    np.testing.assert_allclose(W[z, 1, 0], 2.0 * back[0], rtol=1e-12)
+    np.testing.assert_allclose(W[z, 1, 1:], 1.5 * back[1:], rtol=1e-12)
+
+
+def _linear_state(ndim, n, grad, vel, p=0.9, gamma=1.4, h=(0.1, 0.12, 0.08)):
+    shape = (n,) * ndim
+    idx = np.meshgrid(*[np.arange(n) for _ in range(ndim)], indexing="ij")   # slowest axis first
+    rho = 1.0 + sum(grad[d] * idx[ndim - 1 - d] for d in range(ndim))
+    V = [np.full(shape, vel[d]) for d in range(ndim)]
+    return icgen.prim_to_cons(rho, V, np.full(shape, p), gamma), h
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_hancock_predictor_is_exact_for_linear_advection(ndim):
+    """Density linear in every axis with constant velocity and pressure: every
+    conserved variable is linear, so the limited slopes are the exact
+    undivided differences and the Hancock time mode equals dt dU/dt of the
+    advection solution, -dt sum_d u_d dU/dx_d."""
+    n = 7
+    grad = (0.01, -0.02, 0.015)[:ndim]
+    vel = (0.4, -0.3, 0.2)[:ndim]
+    U, h = _linear_state(ndim, n, grad, vel)
+    c = oracle.make_cfg(ndim, (n, n, n), 2, h, bc=("outflow",) * 3)
+    dt = 0.013
+    W, q = oracle.stage_modes(c, U, dt)
+    nv = ndim + 2
+    assert W.shape[1:] == (1 + ndim, nv) and q.shape[1:] == (2 + ndim, nv)
+    Uz = U.reshape(nv, -1).T
+    # per conserved variable, the undivided difference along axis d of the linear field
+    dU = []
+    for d in range(ndim):
+        s = np.zeros(nv)
+        s[0] = grad[d]
+        for e in range(ndim):
+            s[1 + e] = grad[d] * vel[e]
+        s[nv - 1] = grad[d] * 0.5 * sum(v * v for v in vel)
+        dU.append(s)
+    inner = np.ones((n,) * ndim, dtype=bool)
+    for ax in range(ndim):
+        sl = [slice(None)] * ndim
+        sl[ax] = [0, n - 1]
+        inner[tuple(sl)] = False
+    inner = inner.reshape(-1)
+    for z in np.nonzero(inner)[0]:
+        np.testing.assert_allclose(q[z, 0], Uz[z], rtol=0, atol=0)
+        for d in range(ndim):
+            np.testing.assert_allclose(q[z, 1 + d], dU[d], rtol=1e-12, atol=1e-15)
+        u5 = -sum(dt / h[d] * vel[d] * dU[d] for d in range(ndim))
+        np.testing.assert_allclose(q[z, 1 + ndim], u5, rtol=1e-11, atol=1e-16)
+        np.testing.assert_array_equal(W[z], q[z, :1 + ndim])
+    # the face states of neighbouring zones then agree (a continuous profile at
+    # the half step), so the Riemann solver returns the physical flux and the
+    # whole step is exact: U - sum_d dt/dx_d u_d dU_d, away from the boundary
+    U1 = oracle.step(c, U, dt).reshape(nv, -1).T
+    inner2 = np.ones((n,) * ndim, dtype=bool)
+    for ax in range(ndim):
+        sl = [slice(None)] * ndim
+        sl[ax] = [0, 1, n - 2, n - 1]
+        inner2[tuple(sl)] = False
+    for z in np.nonzero(inner2.reshape(-1))[0]:
+        ex = Uz[z] - sum(dt / h[d] * vel[d] * dU[d] for d in range(ndim))
+        np.testing.assert_allclose(U1[z], ex, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("ndim,solver", [(2, "hll"), (2, "hllc"), (3, "hll"), (3, "rusanov")])
+def test_checkerboard_reduces_to_first_order_godunov(ndim, solver):
+    """A checkerboard density (constant velocity and pressure) has a sign change
+    of every difference in every zone, so all slopes are limited to zero, the
+    time mode vanishes and the step is the first-order Godunov scheme built
+    from the Riemann solver alone."""
+    n = 6
+    shape = (n,) * ndim
+    par = sum(np.meshgrid(*[np.arange(n) for _ in range(ndim)], indexing="ij")) % 2
+    rho = np.where(par == 0, 1.0, 0.6)
+    vel = (0.3, -0.25, 0.15)[:ndim]
+    U = icgen.prim_to_cons(rho, [np.full(shape, v) for v in vel], np.full(shape, 0.8), 1.4)
+    h = (0.1, 0.07, 0.09)
+    c = oracle.make_cfg(ndim, (n, n, n), 2, h, riemann=solver)
+    dt = 0.01
+    W, q = oracle.stage_modes(c, U, dt)
+    assert np.abs(q[:, 1:]).max() == 0.0
+    U1 = oracle.step(c, U, dt)
+    nv = ndim + 2
+    expect = U.copy()
+    for d in range(ndim):
+        ax = ndim - d    # numpy axis of spatial axis d (axis 0 is the variable)
+        Ur = np.roll(U, -1, axis=ax)
+        F = np.zeros_like(U)
+        for ix in np.ndindex(*shape):
+            sl = (slice(None),) + ix
+            F[sl] = oracle.riemann(c, d, U[sl].copy(), Ur[sl].copy())
+        expect -= dt / h[d] * (F - np.roll(F, 1, axis=ax))
+    np.testing.assert_allclose(U1, expect, rtol=1e-13, atol=1e-14)
+    assert U1.shape[0] == nv
+
+
+@pytest.mark.parametrize("ndim,bc", [(2, "periodic"), (3, "outflow")])
+def test_o2_free_stream_is_preserved(ndim, bc):
+    pb = icgen.uniform(n=(7, 6, 5), ndim=ndim, bc=bc, h=(0.1, 0.13, 0.07))
+    c = oracle.cfg_from_problem(pb, 2, riemann="hll")
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    np.testing.assert_allclose(oracle.step(c, pb.U, dt), pb.U, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_o2_conservation_on_a_periodic_box(ndim):
+    pb = icgen.random_smooth(n=(9, 8, 7), ndim=ndim, seed=11, amp=0.3)
+    c = oracle.cfg_from_problem(pb, 2, riemann="hll")
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    U1 = oracle.step(c, pb.U, dt)
+    ax = tuple(range(1, ndim + 1))
+    scale = np.abs(pb.U).sum(axis=ax)
+    assert (np.abs(U1.sum(axis=ax) - pb.U.sum(axis=ax)) / scale).max() < 1e-14
+    assert np.abs(U1 - pb.U).max() > 1e-6
+
+
+@pytest.mark.parametrize("solver", ["hll", "hllc"])
+def test_o2_sod_against_the_exact_riemann_solution(solver):
+    n, t_end = 100, 0.2
+    pb = icgen.sod(n=n, axis=0, ndim=2, ntrans=2)
+    c = oracle.cfg_from_problem(pb, 2, riemann=solver)
+    U, t, _ = oracle.run(c, pb.U, t_end=t_end)
+    assert abs(t - t_end) < 1e-12
+    exact = zone_average_density((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), n, t)
+    num = U[0, 0]
+    assert np.abs(num - exact).mean() < 6e-3
+    assert num.max() < 1.0 + 1e-3 and num.min() > 0.125 - 1e-3
+    np.testing.assert_allclose(U[:, 1], U[:, 0], rtol=0, atol=1e-15)
+    assert np.abs(U[2]).max() < 1e-14
+
+
+def test_o2_sod_is_the_same_along_every_axis():
+    n, steps, ndim = 40, 8, 3
+    res = []
+    for axis in range(ndim):
+        pb = icgen.sod(n=n, axis=axis, ndim=ndim, ntrans=2)
+        c = oracle.cfg_from_problem(pb, 2, riemann="hll")
+        U, _, _ = oracle.run(c, pb.U, nsteps=steps)
+        line = [U[:, 0, 0, :], U[:, 0, :, 0], U[:, :, 0, 0]][axis]
+        perm = list(range(ndim + 2))
+        perm[1], perm[1 + axis] = perm[1 + axis], perm[1]
+        res.append(line[perm])
+    for r in res[1:]:
+        np.testing.assert_allclose(r, res[0], rtol=1e-13, atol=1e-13)
+
+
+def test_o2_z_uniform_3d_equals_2d():
+    """With data independent of z the 3D scheme has zero z-slopes and equal
+    z-fluxes, so it must reproduce the 2D scheme on every z-plane."""
+    pb2 = icgen.random_smooth(n=(8, 7, 1), ndim=2, seed=5, amp=0.3)
+    nz = 3
+    U2 = pb2.U
+    U3 = np.zeros((5, nz) + U2.shape[1:])
+    U3[:3] = U2[:3, None]
+    U3[4] = U2[3][None]
+    c2 = oracle.make_cfg(2, (8, 7, 1), 2, (0.1, 0.1, 0.1), riemann="hll")
+    c3 = oracle.make_cfg(3, (8, 7, nz), 2, (0.1, 0.1, 0.1), riemann="hll")
+    dt = 0.4 * oracle.cfl_dt(c2, U2)[0]
+    A = oracle.step(c2, U2, dt)
+    B = oracle.step(c3, U3, dt)
+    for k in range(nz):
+        np.testing.assert_allclose(B[[0, 1, 2, 4], k], A, rtol=1e-14, atol=1e-15)
+        assert np.abs(B[3, k]).max() == 0.0
+
+
+@pytest.mark.slow
+def test_o2_vortex_design_order():
+    """2D isentropic vortex to t = 1: observed L1 density order at the finest
+    pair at least min(2 - 0.25, the paper's finest second-order value - 0.1)
+    (Table XII)."""
+    errs = []
+    for n in (32, 64, 128):
+        pb = icgen.vortex2d(n)
+        c = oracle.cfg_from_problem(pb, 2, riemann="hll")
+        U, t, _ = oracle.run(c, pb.U, t_end=1.0)
+        errs.append(np.abs(U[0] - icgen.vortex_exact_density(n, t)).mean())
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    paper = _golden_orders()[2]
+    assert orders[-1] >= min(2 - 0.25, paper[-1] - 0.1), (errs, orders)
+    assert orders[-1] <= 3.0
+
+
+def test_o2_positivity_fallback_on_a_cold_flow():
+    """Cold sinusoidal flow: limited conserved slopes give negative face
+    pressures.  Without the fallback the state turns non-physical within two
+    steps; with it the run stays admissible and conservative."""
+    pb = icgen.cold_wave(n=32, ndim=2)
+    off = oracle.cfg_from_problem(pb, 2, riemann="hll", positivity=False)
+    U = pb.U
+    failed = False
+    for _ in range(2):
+        dt, bad = oracle.cfl_dt(off, U)
+        if bad >= 0:
+            failed = True
+            break
+        U = oracle.step(off, U, dt)
+    failed = failed or oracle.cfl_dt(off, U)[1] >= 0
+    assert failed
+    on = oracle.cfg_from_problem(pb, 2, riemann="hll")
+    U, hits = pb.U, 0
+    for _ in range(6):
+        dt, bad = oracle.cfl_dt(on, U)
+        assert bad < 0
+        U, nb = oracle.step_count(on, U, dt)
+        hits += nb
+    assert hits > 0
+    assert oracle.cfl_dt(on, U)[1] < 0
+    tot0, tot1 = pb.U.sum(axis=(1, 2)), U.sum(axis=(1, 2))
+    assert (np.abs(tot1 - tot0) / np.maximum(np.abs(pb.U).sum(axis=(1, 2)), 1.0)).max() < 1e-13
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_o2_zone_list_matches_the_whole_grid(ndim):
+    pb = icgen.random_smooth(n=(6, 5, 4), ndim=ndim, seed=4, amp=0.4, bc="outflow")
+    c = oracle.cfg_from_problem(pb, 2, riemann="hllc")
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    full = oracle.step(c, pb.U, dt)
+    rng = np.random.default_rng(1)
+    n = pb.n
+    ijk = np.stack([rng.integers(0, n[0], 12), rng.integers(0, n[1], 12),
+                    rng.integers(0, n[2], 12)], axis=1)
+    got = oracle.step_zones(c, pb.U, dt, ijk)
+    for s, (i, j, k) in enumerate(ijk):
+        ref = full[:, k, j, i] if ndim == 3 else full[:, j, i]
+        np.testing.assert_allclose(got[s], ref, rtol=1e-15, atol=1e-15)
