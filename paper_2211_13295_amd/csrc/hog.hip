@@ -13,6 +13,7 @@
 #include "hog.h"
 #include "hog_kernels.h"
 #include "hog_gate.h"
+#include "hog_o2.h"
 
 using namespace hog;
 
@@ -57,7 +58,9 @@ int check_cfg(const hog_config* c)
 {
     if (!c) return fail(HOG_EINVAL, "config is NULL");
     if (c->ndim != 2 && c->ndim != 3) return fail(HOG_EINVAL, "ndim must be 2 or 3 (got %d)", c->ndim);
-    if (c->order != 3 && c->order != 4) return fail(HOG_EINVAL, "order must be 3 or 4 (got %d)", c->order);
+    if (c->order < 2 || c->order > 4) return fail(HOG_EINVAL, "order must be 2, 3 or 4 (got %d)", c->order);
+    if (c->order == 2 && c->precision != HOG_FP64)
+        return fail(HOG_EINVAL, "the second-order scheme runs on the FP64 path only");
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(HOG_EINVAL, "zone counts must be >= 1");
     if (c->ndim == 2 && c->nz != 1) return fail(HOG_EINVAL, "nz must be 1 in 2D");
     if (c->riemann < 0 || c->riemann > 2) return fail(HOG_EINVAL, "unknown Riemann solver %d", c->riemann);
@@ -129,11 +132,15 @@ void plan(const hog_config* c, Plan* P)
     P->off_info = take(sizeof(StepInfo));
     P->off_U[0] = take(sizeof(double) * nv * P->pad.vs);
     P->off_U[1] = take(sizeof(double) * nv * P->pad.vs);
-    P->off_A = take(es * (p + 1) * nv * box_size(P->AX));
-    P->off_B = take(es * npairs * nv * box_size(P->BY));
-    P->off_W = (nd == 3) ? take(es * P->ms * nv * box_size(P->R)) : P->off_B;
-    P->off_FP = take(es * nd * 2 * npt * nv * box_size(P->R));
-    for (int d = 0; d < 3; ++d) P->off_F[d] = (d < nd) ? take(sizeof(double) * nv * box_size(P->FB[d])) : 0;
+    // the second-order kernel keeps its modes, face states and fluxes on chip;
+    // face fluxes are stored only for the debug taps
+    const bool o2 = (p == 1);
+    P->off_A = o2 ? 0 : take(es * (p + 1) * nv * box_size(P->AX));
+    P->off_B = o2 ? 0 : take(es * npairs * nv * box_size(P->BY));
+    P->off_W = o2 ? 0 : ((nd == 3) ? take(es * P->ms * nv * box_size(P->R)) : P->off_B);
+    P->off_FP = o2 ? 0 : take(es * nd * 2 * npt * nv * box_size(P->R));
+    for (int d = 0; d < 3; ++d)
+        P->off_F[d] = (d < nd && (!o2 || c->debug)) ? take(sizeof(double) * nv * box_size(P->FB[d])) : 0;
     P->off_Q = c->debug ? take(sizeof(double) * P->mst * nv * box_size(P->R)) : 0;
     P->off_stage = take(sizeof(double) * nv * box_size(P->I));
     P->off_gate = take(nd == 3 ? sizeof(GateParams<3>) : sizeof(GateParams<2>));
@@ -284,8 +291,50 @@ int enqueue_step_t(hog_grid* g, double dt_user)
     return launch_check("step");
 }
 
+// Planes of the march axis per workgroup of the second-order kernel: enough
+// workgroups for about eight per compute unit, at least 8 planes per chunk.
+template <int D>
+int o2_chunk(const Plan& L)
+{
+    using S = O2Shape<D>;
+    const long long cols = (long long)((L.n[0] + S::TX - 3) / (S::TX - 2)) *
+                           (D == 3 ? (L.n[1] + S::TY - 3) / (S::TY - 2) : 1);
+    const int nm = L.n[D - 1];
+    const long long want = 2048;
+    long long zc = (nm * cols + want - 1) / want;
+    if (zc < 8) zc = 8;
+    if (zc > nm) zc = nm;
+    return (int)zc;
+}
+
+template <int D>
+int enqueue_o2(hog_grid* g, double dt_user)
+{
+    using S = O2Shape<D>;
+    const Plan& L = g->P;
+    hipStream_t s = g->stream;
+    const double* h = g->h;
+    k_begin_step<<<1, 1, 0, s>>>(g->info, dt_user, g->cfg.cfl, h[0], h[1], h[2]);
+    O2Args a;
+    for (int d = 0; d < 3; ++d) { a.n[d] = L.n[d]; a.bc[d] = g->cfg.bc[d]; a.ih[d] = 1.0 / h[d]; }
+    a.zc = o2_chunk<D>(L);
+    a.solver = g->cfg.riemann;
+    a.positivity = g->cfg.positivity;
+    a.gamma = g->cfg.gamma;
+    const long long nb = (long long)((L.n[0] + S::TX - 3) / (S::TX - 2)) *
+                         (D == 3 ? (L.n[1] + S::TY - 3) / (S::TY - 2) : 1) * ((L.n[D - 1] + a.zc - 1) / a.zc);
+    {
+        StageMark m(g, 2);
+        k_o2_step<D><<<xcd_blocks(nb), S::TX * S::TY, 0, s>>>(g->U[g->cur], g->U[g->cur ^ 1], L.pad, a, g->info,
+                                                             static_cast<double*>(g->Q), L.R, g->F[0], L.FB[0],
+                                                             g->F[1], L.FB[1], g->F[2], L.FB[2]);
+    }
+    return launch_check("second-order step");
+}
+
 int enqueue_step(hog_grid* g, double dt_user)
 {
+    if (g->P.p == 1) return g->P.nd == 3 ? enqueue_o2<3>(g, dt_user) : enqueue_o2<2>(g, dt_user);
     const int key = (g->cfg.precision == HOG_MIXED ? 100 : 0) + g->P.nd * 10 + g->P.p;
     switch (key) {
     case 22: return enqueue_step_t<2, 2, double>(g, dt_user);
@@ -393,11 +442,12 @@ int hog_create(const hog_config* cfg, void* workspace, size_t bytes, void* hip_s
     g->info = reinterpret_cast<StepInfo*>(g->ws + P.off_info);
     g->U[0] = reinterpret_cast<double*>(g->ws + P.off_U[0]);
     g->U[1] = reinterpret_cast<double*>(g->ws + P.off_U[1]);
-    g->A = g->ws + P.off_A;
-    g->B = g->ws + P.off_B;
-    g->W = g->ws + P.off_W;
-    g->FP = g->ws + P.off_FP;
-    for (int d = 0; d < 3; ++d) g->F[d] = (d < P.nd) ? reinterpret_cast<double*>(g->ws + P.off_F[d]) : nullptr;
+    g->A = (P.p > 1) ? g->ws + P.off_A : nullptr;
+    g->B = (P.p > 1) ? g->ws + P.off_B : nullptr;
+    g->W = (P.p > 1) ? g->ws + P.off_W : nullptr;
+    g->FP = (P.p > 1) ? g->ws + P.off_FP : nullptr;
+    for (int d = 0; d < 3; ++d)
+        g->F[d] = (d < P.nd && (P.p > 1 || cfg->debug)) ? reinterpret_cast<double*>(g->ws + P.off_F[d]) : nullptr;
     g->Q = cfg->debug ? static_cast<void*>(g->ws + P.off_Q) : nullptr;
     g->stage = reinterpret_cast<double*>(g->ws + P.off_stage);
     g->gate_on = g->gate_fixed = g->gate_net = false;
@@ -624,7 +674,8 @@ int hog_debug_tap(hog_grid* g, int tap, void* dst, size_t bytes)
     const int nv = L.nv;
     if (tap == HOG_TAP_MODES || tap == HOG_TAP_STMODES) {
         const int nm = (tap == HOG_TAP_MODES) ? L.ms : L.mst;
-        const void* src = (tap == HOG_TAP_MODES) ? g->W : g->Q;
+        // at second order the mean and slopes are the first 1 + nd space-time modes
+        const void* src = (tap == HOG_TAP_MODES && L.p > 1) ? g->W : g->Q;
         if (!src) return fail(HOG_EINVAL, "space-time modes are kept only with debug = 1");
         if (bytes < sizeof(double) * N * nm * nv) return fail(HOG_EINVAL, "tap buffer too small");
         const size_t n = (size_t)nm * nv * nR;
@@ -706,6 +757,7 @@ int hog_set_gate(hog_grid* g, const float* params, double theta)
     if (!g) return fail(HOG_EINVAL, "NULL handle");
     g->gate_fixed = false;
     if (!params) { g->gate_on = g->gate_net = false; return HOG_OK; }
+    if (g->P.p == 1) return fail(HOG_EINVAL, "the second-order scheme has no WENO weights to gate");
     if (!(theta > 0.0 && theta < 1.0)) return fail(HOG_EINVAL, "theta must be in (0, 1)");
     const int rc = (g->P.nd == 3) ? set_gate_t<3>(g, params, theta) : set_gate_t<2>(g, params, theta);
     if (rc) { g->gate_on = g->gate_net = false; return rc; }
@@ -721,6 +773,7 @@ int hog_set_gate_flags(hog_grid* g, const unsigned char* flags)
         g->gate_on = g->gate_net;
         return HOG_OK;
     }
+    if (g->P.p == 1) return fail(HOG_EINVAL, "the second-order scheme has no WENO weights to gate");
     const long long N = box_size(g->P.I);
     for (long long i = 0; i < N; ++i)
         if (flags[i] > 1) return fail(HOG_EINVAL, "flags must be 0 or 1 (zone %lld)", i);
@@ -788,6 +841,7 @@ int hog_harvest(hog_grid* g, const long long* zones, long long n, float* feature
     if (!g || !zones || !features || !maxdev || n < 0) return fail(HOG_EINVAL, "bad arguments");
     if (!g->have_state) return fail(HOG_ESTATE, "no state set");
     if (g->cfg.precision != HOG_FP64) return fail(HOG_EINVAL, "harvest runs on the FP64 path");
+    if (g->P.p == 1) return fail(HOG_EINVAL, "the second-order scheme has no WENO weights to harvest");
     if (n == 0) return HOG_OK;
     enqueue_ghost(g);
     switch (g->P.nd * 10 + g->P.p) {

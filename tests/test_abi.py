@@ -47,6 +47,17 @@ def test_invalid_configs_are_rejected_without_a_device():
     bad = hog.make_config(3, (2, 8, 8), 4, (0.1, 0.1, 0.1))   # periodic axis too short
     with pytest.raises(hog.HogError):
         hog.workspace_size(bad)
+    # second order: FP64 only, and its plan holds no reconstruction or predictor arrays
+    o2 = hog.make_config(3, (8, 8, 8), 2, (0.1, 0.1, 0.1))
+    assert 0 < hog.workspace_size(o2) < hog.workspace_size(c) // 4
+    for order in (1, 5):
+        bad = hog.make_config(3, (8, 8, 8), 4, (0.1, 0.1, 0.1))
+        bad.order = order
+        with pytest.raises(hog.HogError):
+            hog.workspace_size(bad)
+    with pytest.raises(hog.HogError) as e:
+        hog.workspace_size(hog.make_config(3, (8, 8, 8), 2, (0.1, 0.1, 0.1), precision="mixed"))
+    assert e.value.code == hog.HOG_EINVAL
 
 
 def test_product_package_does_not_import_the_oracle():
