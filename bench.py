@@ -101,6 +101,34 @@ def predictor_flops(D, P):
     return total
 
 
+def o2_flops(D, n, solver="hll"):
+    """Algorithmic FP64 operations of one second-order step of an n^D periodic
+    grid (each add, mul, div, sqrt, min, max, abs-scale counts 1, an FMA 2):
+
+    modes, on the interior grown by one zone per axis (their faces bound the
+    interior): per axis and variable the MC slope (two differences, the sum,
+    its half, two compression products, two mins: 8), the face-centre values
+    U -+ S/2 (2 x 2), two physical fluxes (3D + 8 each: 1/rho, kinetic
+    energy, pressure, normal velocity, momentum and energy fluxes) and the
+    time-mode sum lam (Fp - Fm) (3 per variable); face states U -+ S/2 + U5/2
+    (3 per variable and face, plus U5/2) and their pressures for the
+    admissibility check (2D + 3 each);
+    Riemann problems, one per face ((n + 1) n^(D-1) per axis): HLL with
+    Einfeldt-Roe bounds = two fluxes, two sound speeds, the Roe averages and
+    bounds, and the HLL combination (7 per variable);
+    update and CFL, per interior zone: three operations per axis and variable
+    and the signal speed (3D + 8)."""
+    NV = D + 2
+    flux = 3 * D + 8
+    per_axis = 15 * NV + 2 * flux
+    modes = D * per_axis + 2 * D * NV * 3 + NV + 2 * D * (2 * D + 3)
+    riem = {"hll": 2 * flux + 6 + 2 + 2 + 4 + 4 * D + (2 * D - 1) + 4 + 4 + 6 + 2 + 7 * NV + 1}[solver]
+    upd = 3 * D * NV + 3 * D + 8
+    zones_m = (n + 2) ** D
+    faces = D * (n + 1) * n ** (D - 1)
+    return modes * zones_m + riem * faces + upd * n ** D
+
+
 def kernel_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -172,6 +200,80 @@ def write_traffic(fetch_csv, write_csv, n=128):
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
+
+
+def cpu_baseline_o2(seconds, n=64):
+    """The CPU oracle's second-order scheme timed on this host on a bounded
+    sample: whole steps of the same 3D workload at 64^3."""
+    import icgen
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    pb = icgen.vortex3d_perturbed(n=n, seed=2)
+    c = oracle.cfg_from_problem(pb, 2, riemann="hll")
+    U = pb.U
+    dt, _ = oracle.cfl_dt(c, U)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        U = oracle.step(c, U, dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 200:
+            break
+    return {"value": n ** 3 * steps / el, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full second-order steps of the same 3D workload at {n}^3 "
+                      f"({el:.1f} s, OpenMP threads={threads})"}
+
+
+def second_order_line(hog, torch, args):
+    """Benchmark line of the second-order scheme (Figs. 3-7, HLL) on the same
+    128^3 workload: one fused kernel per step; roofline of that kernel against
+    its operation count (o2_flops) and its compulsory HBM bytes (state read
+    once, new state written once: 80 B per zone)."""
+    import icgen
+    n = args.n
+    pb = icgen.vortex3d_perturbed(n=n, seed=2)
+    g = hog.Grid.from_problem(pb, 2, riemann="hll")
+    if args.warmup > 0:
+        g.advance(args.warmup)
+    g.set_state(pb.U)
+    torch.cuda.synchronize()
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.advance(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile_read()
+    g.profile(False)
+    g.close()
+    elapsed = t1 - t0
+    zones = n ** 3
+    k_ms, k_calls = prof["predictor"]
+    avg_s = k_ms / 1e3 / max(k_calls, 1)
+    flops = o2_flops(3, n)
+    achieved = flops / avg_s / 1e12
+    hbm_bytes = zones * 5 * 8 * 2
+    out = {
+        "metric": METRIC, "value": zones * args.steps / elapsed, "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"3D Euler isentropic vortex extruded along z + seeded density modes "
+                               f"(amp 1e-2, 4 per axis), {n}^3 periodic [0,10]^3, second-order scheme of "
+                               f"Figs. 3-7 (MC limiter 2/1.5, Hancock time mode, midpoint HLL), CFL 0.4, FP64",
+                   "zones": zones, "order": 2, "riemann": "hll", "precision": "fp64"},
+        "roofline": {"bound": "alu", "kernel": "k_o2_step (fused second-order step)", "achieved": achieved,
+                     "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS,
+                     "traffic": None, "alg_flops_per_launch": flops, "alg_flops_per_zone": flops / zones,
+                     "avg_launch_ms": avg_s * 1e3,
+                     "hbm": {"alg_bytes_per_launch": hbm_bytes, "achieved_GBps": hbm_bytes / avg_s / 1e9,
+                             "peak_GBps": 8000.0, "frac": hbm_bytes / avg_s / 8e12}},
+        "stages_ms_per_launch": {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_o2(args.cpu_seconds)
+    return out
 
 
 def cpu_baseline(order, seconds):
@@ -436,6 +538,9 @@ def main():
     ap.add_argument("--gate-ablation", choices=["multiblast256", "fourquad384"],
                     help="instead of the benchmark line: full WENO / trained gate / all linear / random gate "
                          "on the mixed path of a full-size shock workload; prints one JSON line")
+    ap.add_argument("--second-order", action="store_true",
+                    help="instead of the benchmark line: the second-order scheme of Figs. 3-7 (HLL) on the "
+                         "same workload; prints one JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the predictor traffic record from two rocprofv3 counter files and exit")
     args = ap.parse_args()
@@ -458,6 +563,9 @@ def main():
     if args.gate_ablation:
         steps = 100 if args.gate_ablation == "multiblast256" else 200
         print(json.dumps(gate_ablation(hog, torch, args.gate_ablation, steps, 20)), flush=True)
+        return
+    if args.second_order:
+        print(json.dumps(second_order_line(hog, torch, args)), flush=True)
         return
     if args.shock_workload:
         steps = 100 if args.shock_workload == "multiblast256" else 200

@@ -8,6 +8,16 @@
  *   an ADER predictor that extends each zone polynomial in time,
  *   a Riemann-solver (HLLC/HLL/Rusanov) corrector with a conservative
  *   flux-difference update, and the CFL time step of the new state.
+ * With order = 2 the step is instead the paper's own second-order scheme
+ * (Sec. II.1, Figs. 3-7): slopes of the conserved variables from a
+ * monotonised-central limiter with compression factor 2 for the density and
+ * 1.5 for the other variables (Fig. 3), a pointwise predictor of the time
+ * mode (Fig. 4; its body is not printed and is read as the Hancock step:
+ * minus dt/dx_d times the flux difference between the zone's face-centre
+ * values U +- S_d/2, summed over the axes), one Riemann problem per face at
+ * the face centre and half time step with the states U +- S_d/2 + U5/2
+ * (Fig. 5), and the flux-difference update (Figs. 6-7).  It runs as one fused
+ * kernel per step on the FP64 path.
  * The state lives in device memory between calls: the paper's per-step host
  * round trip of the zone means (its "U_skinny" transfer, Sec. II.1, Fig. 1)
  * only happens when the caller asks for it with hog_get_state().
@@ -60,9 +70,11 @@ enum { HOG_HOST = 0, HOG_DEVICE = 1 };                 /* where a user buffer li
 
 /* Debug taps (hog_debug_tap): intermediates of the last hog_step(). */
 enum {
-    HOG_TAP_MODES = 1,   /* spatial modes after reconstruction: double [N][ns][nv] */
+    HOG_TAP_MODES = 1,   /* spatial modes after reconstruction: double [N][ns][nv]
+                            (at order 2: mean and limited undivided slopes, debug = 1) */
     HOG_TAP_STMODES = 2, /* space-time modes after the predictor: double [N][nst][nv]
-                            (needs debug = 1 in the config) */
+                            (needs debug = 1 in the config; at order 2 the last
+                            mode is the time mode U5 = dt dU/dt of Fig. 4) */
     HOG_TAP_FLUX_X = 3,  /* face fluxes: double [nv][nz][ny][nx+1] (x faces)      */
     HOG_TAP_FLUX_Y = 4,  /*              double [nv][nz][ny+1][nx]                */
     HOG_TAP_FLUX_Z = 5   /*              double [nv][nz+1][ny][nx]                */
@@ -77,7 +89,8 @@ enum {
 typedef struct hog_config {
     int ndim;            /* 2 or 3 */
     int nx, ny, nz;      /* interior zones per axis (nz = 1 in 2D), each >= 1 */
-    int order;           /* 3 or 4 (polynomial degree p = order - 1) */
+    int order;           /* 2, 3 or 4 (polynomial degree p = order - 1); 2 is the
+                            scheme of Figs. 3-7 and needs precision HOG_FP64 */
     int riemann;         /* HOG_HLLC | HOG_HLL | HOG_RUSANOV */
     int bc[3];           /* per axis HOG_PERIODIC | HOG_OUTFLOW */
     int precision;       /* HOG_FP64 | HOG_MIXED */
@@ -85,7 +98,9 @@ typedef struct hog_config {
     int debug;           /* 1: keep the space-time modes for HOG_TAP_STMODES */
     int positivity;      /* 1: a zone whose predictor meets rho <= 0, p <= 0 or a
                             non-finite state at any quadrature node or face point
-                            falls back to its zone mean (first order) for that step */
+                            falls back to its zone mean (first order) for that step;
+                            at order 2 the points checked are the face-centre values
+                            U +- S_d/2 and the face states U +- S_d/2 + U5/2 */
     int reserved[3];     /* must be 0 */
     double gamma;        /* ratio of specific heats, > 1 */
     double dx, dy, dz;   /* zone widths (dz ignored in 2D), > 0 */
@@ -194,7 +209,8 @@ int hog_gate_param_count(int ndim, int* count);
  * the 1D WENO applications centred at an interior zone whose output
  * probability is >= theta use the linear weights (no smoothness indicators);
  * applications centred outside the interior keep the nonlinear weights.
- * params = NULL disables the gate.  Synchronises.  Errors: HOG_EINVAL. */
+ * params = NULL disables the gate.  Synchronises.  Errors: HOG_EINVAL (also
+ * for a non-NULL params at order 2, which has no WENO weights). */
 int hog_set_gate(hog_grid* g, const float* params, double theta);
 
 /* Evaluate the gate on the current state: host arrays of nx*ny*nz logits
@@ -208,7 +224,8 @@ int hog_gate_eval(hog_grid* g, float* logits, unsigned char* flags);
  * linear weights).  For ablations of the gate: all zones linear, or a
  * random selection of the network's smooth fraction.  flags = NULL returns
  * to the network loaded by hog_set_gate, or to no gate; hog_set_gate also
- * clears fixed flags.  Synchronises.  Errors: HOG_EINVAL (a flag not 0/1). */
+ * clears fixed flags.  Synchronises.  Errors: HOG_EINVAL (a flag not 0/1, or
+ * non-NULL flags at order 2). */
 int hog_set_gate_flags(hog_grid* g, const unsigned char* flags);
 
 /* Training samples from the current state (FP64 path only): for the n
@@ -217,7 +234,7 @@ int hog_set_gate_flags(hog_grid* g, const unsigned char* flags);
  * maxdev (device, n floats), the largest |omega_k/gamma_k - 1| of the
  * nonlinear WENO weights over the variables and the 1D applications centred
  * at the zone (a zone is labelled smooth when it is <= 0.25).  Stream-ordered,
- * no synchronisation.  Errors: HOG_EINVAL, HOG_ESTATE. */
+ * no synchronisation.  Errors: HOG_EINVAL (also at order 2), HOG_ESTATE. */
 int hog_harvest(hog_grid* g, const long long* zones, long long n, float* features, float* maxdev);
 
 /* Training of the gate network on the GPU (FP32 masters, Adam, BF16-rounded

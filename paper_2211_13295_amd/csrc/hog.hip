@@ -2,6 +2,7 @@
 // planning, argument checks and the per-step launch sequence on the caller's
 // HIP stream.  The kernels are in hog_kernels.h.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -162,6 +163,7 @@ struct hog_grid {
     long long last_bad;
     WenoArgs wa;
     double h[3];
+    int cus;          // compute units of the device (workgroup scheduling of the fused kernels)
     StepInfo* info;
     double* U[2];
     void *A, *B, *W, *FP, *Q;     // element type: double (FP64) or float (mixed)
@@ -291,20 +293,22 @@ int enqueue_step_t(hog_grid* g, double dt_user)
     return launch_check("step");
 }
 
-// Planes of the march axis per workgroup of the second-order kernel: enough
-// workgroups for about eight per compute unit, at least 8 planes per chunk.
+// Planes of the march axis per workgroup of the second-order kernel.  Two
+// workgroups are resident per compute unit; the march is cut into as many
+// chunks as fill whole rounds of resident workgroups (a partial last round
+// leaves compute units idle), using as few rounds as keep the chunks at about
+// 32 planes or less (each chunk recomputes two extra planes of modes).
 template <int D>
-int o2_chunk(const Plan& L)
+int o2_chunk(const Plan& L, int cus)
 {
     using S = O2Shape<D>;
     const long long cols = (long long)((L.n[0] + S::TX - 3) / (S::TX - 2)) *
                            (D == 3 ? (L.n[1] + S::TY - 3) / (S::TY - 2) : 1);
-    const int nm = L.n[D - 1];
-    const long long want = 2048;
-    long long zc = (nm * cols + want - 1) / want;
-    if (zc < 8) zc = 8;
-    if (zc > nm) zc = nm;
-    return (int)zc;
+    const long long nm = L.n[D - 1];
+    const long long slots = 2ll * cus;
+    const long long rounds = std::max(1ll, (nm * cols + slots * 32 - 1) / (slots * 32));
+    const long long chunks = std::max(1ll, rounds * slots / cols);
+    return (int)std::min(nm, (nm + chunks - 1) / chunks);
 }
 
 template <int D>
@@ -317,17 +321,21 @@ int enqueue_o2(hog_grid* g, double dt_user)
     k_begin_step<<<1, 1, 0, s>>>(g->info, dt_user, g->cfg.cfl, h[0], h[1], h[2]);
     O2Args a;
     for (int d = 0; d < 3; ++d) { a.n[d] = L.n[d]; a.bc[d] = g->cfg.bc[d]; a.ih[d] = 1.0 / h[d]; }
-    a.zc = o2_chunk<D>(L);
-    a.solver = g->cfg.riemann;
+    a.zc = o2_chunk<D>(L, g->cus);
     a.positivity = g->cfg.positivity;
     a.gamma = g->cfg.gamma;
     const long long nb = (long long)((L.n[0] + S::TX - 3) / (S::TX - 2)) *
                          (D == 3 ? (L.n[1] + S::TY - 3) / (S::TY - 2) : 1) * ((L.n[D - 1] + a.zc - 1) / a.zc);
     {
         StageMark m(g, 2);
-        k_o2_step<D><<<xcd_blocks(nb), S::TX * S::TY, 0, s>>>(g->U[g->cur], g->U[g->cur ^ 1], L.pad, a, g->info,
-                                                             static_cast<double*>(g->Q), L.R, g->F[0], L.FB[0],
-                                                             g->F[1], L.FB[1], g->F[2], L.FB[2]);
+        auto launch = [&](auto kernel) {
+            kernel<<<xcd_blocks(nb), S::TX * S::TY, 0, s>>>(g->U[g->cur], g->U[g->cur ^ 1], L.pad, a, g->info,
+                                                           static_cast<double*>(g->Q), L.R, g->F[0], L.FB[0],
+                                                           g->F[1], L.FB[1], g->F[2], L.FB[2]);
+        };
+        if (g->cfg.riemann == HOG_HLLC) launch(k_o2_step<D, HOG_HLLC>);
+        else if (g->cfg.riemann == HOG_HLL) launch(k_o2_step<D, HOG_HLL>);
+        else launch(k_o2_step<D, HOG_RUSANOV>);
     }
     return launch_check("second-order step");
 }
@@ -419,6 +427,7 @@ int hog_create(const hog_config* cfg, void* workspace, size_t bytes, void* hip_s
     if (!g) return fail(HOG_ENOMEM, "host allocation failed");
     g->cfg = *cfg;
     g->P = P;
+    g->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     g->stream = static_cast<hipStream_t>(hip_stream);
     g->ws = static_cast<char*>(workspace);
     g->ws_bytes = bytes;

@@ -52,7 +52,6 @@ struct O2Args {
     int n[3];        // interior zones per axis (n[2] = 1 in 2D)
     int bc[3];
     int zc;          // planes of the march axis per workgroup
-    int solver;      // 0 HLLC, 1 HLL, 2 Rusanov
     int positivity;  // 1: zones with an inadmissible face value fall back to their mean
     double gamma;
     double ih[3];    // 1 / dx_d
@@ -79,8 +78,8 @@ __device__ __forceinline__ bool o2_modes(const double* u, NB&& nb, const double*
             Wm[v] = u[v] - 0.5 * S[d][v];
             Wp[v] = u[v] + 0.5 * S[d][v];
         }
-        flux_dir<D, double>(Wm, gm1, d, Fm, pm, um);
-        flux_dir<D, double>(Wp, gm1, d, Fp, pp, up);
+        flux_dir<D, double, true>(Wm, gm1, d, Fm, pm, um);
+        flux_dir<D, double, true>(Wp, gm1, d, Fp, pp, up);
         ok = ok && Wm[0] > 0.0 && pm > 0.0 && isfinite(Wm[0]) && isfinite(pm);
         ok = ok && Wp[0] > 0.0 && pp > 0.0 && isfinite(Wp[0]) && isfinite(pp);
 #pragma unroll
@@ -94,12 +93,12 @@ __device__ __forceinline__ bool o2_modes(const double* u, NB&& nb, const double*
             Wm[v] = u[v] - 0.5 * S[d][v] + 0.5 * T[v];
             Wp[v] = u[v] + 0.5 * S[d][v] + 0.5 * T[v];
         }
-        ok = ok && admissible<D, double>(Wm, gm1) && admissible<D, double>(Wp, gm1);
+        ok = ok && admissible<D, double, true>(Wm, gm1) && admissible<D, double, true>(Wp, gm1);
     }
     return ok;
 }
 
-template <int D>
+template <int D, int SOLVER>
 __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ Uo, double* __restrict__ Un, Pad p,
                                                  O2Args a, StepInfo* info, double* __restrict__ Q, Box R,
                                                  double* __restrict__ Fx, Box FBx, double* __restrict__ Fy,
@@ -164,9 +163,9 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
     const int gx_own = ci, gy_own = cj;
     const int gx_ring = x0 - 2 + rx, gy_ring = y0 - 2 + ry;
 
-    double Um[NV], Uc[NV], Up[NV], Uq[NV], Rp[NV], Rq[NV];
+    double Um[NV], Uc[NV], Up[NV], Uq[NV], Rq[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) { Uq[v] = 0.0; Rp[v] = 0.0; Rq[v] = 0.0; }
+    for (int v = 0; v < NV; ++v) { Uq[v] = 0.0; Rq[v] = 0.0; }
     auto load = [&](double* dst, int x, int y, int m) {
         const long long g = gidx(x, y, m);
 #pragma unroll
@@ -181,7 +180,6 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
         load(t, gx_ring, gy_ring, m0 - 1);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sU[v][ring_l] = t[v];
-        load(Rp, gx_ring, gy_ring, m0);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) sU[v][own_l] = Uc[v];
@@ -196,11 +194,10 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
     const long long nR = box_size(R);
 
     for (int m = m0 - 1; m <= m1; ++m) {
-        // plane m+2 for the next iteration (its LDS copy is written after barrier B)
-        if (m + 2 <= m1 + 1) {
-            load(Uq, gx_own, gy_own, m + 2);
-            if (tid < NRING) load(Rq, gx_ring, gy_ring, m + 2);
-        }
+        // own zone of plane m+2 for the next iteration; ring of plane m+1 for the
+        // LDS copy of that plane written after barrier B
+        if (m + 2 <= m1 + 1) load(Uq, gx_own, gy_own, m + 2);
+        if (tid < NRING) load(Rq, gx_ring, gy_ring, m + 1);
         __syncthreads();   // A: plane m complete in LDS
         const bool xy_plane = m >= m0 && m < m1;      // planes whose x / y faces are needed
         double S[D][NV], T[NV];
@@ -232,8 +229,9 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
                 Q[((long long)(1 + D) * NV + v) * nR + r] = T[v];
             }
         }
-        // face states at the half step (Fig. 5): +/- faces along each axis
-        double xm[NV], ym[NV], zm[NV], zp[NV];
+        // face states at the half step (Fig. 5): +/- faces along each axis; the
+        // +x / +y states go to the neighbours through LDS
+        double xm[NV], ym[NV], zm[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double h = 0.5 * T[v];
@@ -244,37 +242,14 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
                 sYp[v][tid] = Uc[v] + 0.5 * S[1][v] + h;
             }
             zm[v] = Uc[v] - 0.5 * S[D - 1][v] + h;
-            zp[v] = Uc[v] + 0.5 * S[D - 1][v] + h;
         }
-        __syncthreads();   // B: face states visible; plane m no longer read
+        // face m - 1/2 along the march axis lies between planes m-1 and m: both
+        // states are this thread's, so it is solved before the exchange
+        const bool zface = m >= m0;
+        double Fzm[NV];
+        if (zface) riemann<D, double, true>(zp_prev, zm, D - 1, SOLVER, a.gamma, Fzm);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sU[v][own_l] = Up[v];
-        if (tid < NRING) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) sU[v][ring_l] = Rp[v];
-        }
-        double Fxm[NV], Fym[NV], Fzm[NV];
-        if (xy_plane && tx >= 1) {
-            double L[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) L[v] = sXp[v][tid - 1];
-            riemann<D, double>(L, xm, 0, a.solver, a.gamma, Fxm);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) sFx[v][tid] = Fxm[v];
-        }
-        if constexpr (D == 3) {
-            if (xy_plane && ty >= 1) {
-                double L[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) L[v] = sYp[v][tid - TX];
-                riemann<D, double>(L, ym, 1, a.solver, a.gamma, Fym);
-#pragma unroll
-                for (int v = 0; v < NV; ++v) sFy[v][tid] = Fym[v];
-            }
-        }
-        const bool zface = m >= m0;                 // face m - 1/2 lies between planes m-1 and m
-        if (zface) riemann<D, double>(zp_prev, zm, D - 1, a.solver, a.gamma, Fzm);
-        __syncthreads();   // C: -x / -y fluxes visible
+        for (int v = 0; v < NV; ++v) zp_prev[v] = Uc[v] + 0.5 * S[D - 1][v] + 0.5 * T[v];
         if (zface && m - 1 >= m0 && inner) {
             // update of the zone of plane m-1: increment of Fig. 6 added to the mean (Fig. 7)
             double u[NV];
@@ -285,10 +260,49 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
 #pragma unroll
             for (int v = 0; v < NV; ++v) Un[v * p.vs + pi] = u[v];
             bool ok = true;
-            const double s = signal_speed<D>(u, a.gamma, a.ih[0], a.ih[1], a.ih[2], ok);
-            if (ok) smax = fmax(smax, s);
+            const double sp = signal_speed<D>(u, a.gamma, a.ih[0], a.ih[1], a.ih[2], ok);
+            if (ok) smax = fmax(smax, sp);
             else atomicMin(&info->bad, (unsigned long long)(((long long)k * n1 + j) * n0 + i));
         }
+        if (Fx && zface && inner) {
+            Box FB = (D == 3) ? FBz : FBy;
+            double* Fm = (D == 3) ? Fz : Fy;
+            const int i = ci, j = (D == 3) ? cj : m - 1, k = (D == 3) ? m - 1 : 0;
+            const long long nF = box_size(FB);
+            const long long f = box_index(FB, i, j, k);    // face m - 1/2
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Fm[v * nF + f] = Fzm[v];
+        }
+        // the -z flux term of this plane's zone; the x / y terms follow below
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = zface ? lam[D - 1] * Fzm[v] : 0.0;
+        __syncthreads();   // B: face states visible; plane m no longer read
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sU[v][own_l] = Up[v];
+        if (tid < NRING) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sU[v][ring_l] = Rq[v];
+        }
+        double Fxm[NV], Fym[NV];
+        if (xy_plane && tx >= 1) {
+            double L[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) L[v] = sXp[v][tid - 1];
+            riemann<D, double, true>(L, xm, 0, SOLVER, a.gamma, Fxm);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sFx[v][tid] = Fxm[v];
+        }
+        if constexpr (D == 3) {
+            if (xy_plane && ty >= 1) {
+                double L[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) L[v] = sYp[v][tid - TX];
+                riemann<D, double, true>(L, ym, 1, SOLVER, a.gamma, Fym);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sFy[v][tid] = Fym[v];
+            }
+        }
+        __syncthreads();   // C: -x / -y fluxes visible
         if (Fx && xy_plane && inner) {
             const int i = ci, j = (D == 3) ? cj : m, k = (D == 3) ? m : 0;
             const long long nF = box_size(FBx);
@@ -314,32 +328,20 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
                 (void)Fy;
             }
         }
-        if (Fx && zface && inner) {
-            Box FB = (D == 3) ? FBz : FBy;
-            double* Fm = (D == 3) ? Fz : Fy;
-            const int i = ci, j = (D == 3) ? cj : m - 1, k = (D == 3) ? m - 1 : 0;
-            const long long nF = box_size(FB);
-            const long long f = box_index(FB, i, j, k);    // face m - 1/2
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Fm[v * nF + f] = Fzm[v];
-        }
         // increment of this plane's zone so far, completed one plane later
         if (xy_plane && inner) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double fxp = sFx[v][tid + 1];
-                double d = -lam[0] * (fxp - Fxm[v]);
+                double d = -lam[0] * (sFx[v][tid + 1] - Fxm[v]);
                 if constexpr (D == 3) d -= lam[1] * (sFy[v][tid + TX] - Fym[v]);
-                acc[v] = d + lam[D - 1] * Fzm[v];
+                acc[v] = d + acc[v];
             }
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            zp_prev[v] = zp[v];
             Um[v] = Uc[v];
             Uc[v] = Up[v];
             Up[v] = Uq[v];
-            Rp[v] = Rq[v];
         }
     }
     if (a.positivity && nfb) atomicAdd(&info->fallback, nfb);

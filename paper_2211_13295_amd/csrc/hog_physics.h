@@ -17,23 +17,6 @@ struct WenoArgs {
 // The device routines below are templates on the arithmetic type T: double
 // on the FP64 path, float where the mixed path computes in FP32.
 
-// Pressure of an ideal gas from the conserved variables of D dimensions.
-template <int D, typename T = double>
-__device__ __forceinline__ T pressure(const T* U, T gm1)
-{
-    T ke = T(0);
-#pragma unroll
-    for (int d = 0; d < D; ++d) ke += U[1 + d] * U[1 + d];
-    return gm1 * (U[D + 1] - T(0.5) * ke / U[0]);
-}
-
-// rho > 0, p > 0 and both finite.
-template <int D, typename T = double>
-__device__ __forceinline__ bool admissible(const T* U, T gm1)
-{
-    const T p = pressure<D, T>(U, gm1);
-    return U[0] > T(0) && p > T(0) && isfinite(U[0]) && isfinite(p);
-}
 
 // Physical fluxes of the Euler equations along all D axes at one point;
 // returns whether the state is admissible (rho > 0, p > 0, finite).
@@ -73,11 +56,39 @@ __device__ __forceinline__ bool fluxes(const T* U, T gm1, T (*F)[D + 2])
     return rho > T(0) && p > T(0) && isfinite(rho) && isfinite(p);
 }
 
+// a / b: the division, or with RCP a times the Newton-refined reciprocal of b
+// (recip above; a few ulp instead of correctly rounded, about half the
+// instructions of an FP64 division).
+template <bool RCP, typename T>
+__device__ __forceinline__ T dv(T a, T b)
+{
+    if constexpr (RCP) return a * recip(b);
+    else return a / b;
+}
+
+// Pressure of an ideal gas from the conserved variables of D dimensions.
+template <int D, typename T = double, bool RCP = false>
+__device__ __forceinline__ T pressure(const T* U, T gm1)
+{
+    T ke = T(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) ke += U[1 + d] * U[1 + d];
+    return gm1 * (U[D + 1] - dv<RCP>(T(0.5) * ke, U[0]));
+}
+
+// rho > 0, p > 0 and both finite.
+template <int D, typename T = double, bool RCP = false>
+__device__ __forceinline__ bool admissible(const T* U, T gm1)
+{
+    const T p = pressure<D, T, RCP>(U, gm1);
+    return U[0] > T(0) && p > T(0) && isfinite(U[0]) && isfinite(p);
+}
+
 // Flux of one axis.
-template <int D, typename T = double>
+template <int D, typename T = double, bool RCP = false>
 __device__ __forceinline__ void flux_dir(const T* U, T gm1, int dir, T* F, T& p, T& un)
 {
-    const T ir = T(1) / U[0];
+    const T ir = dv<RCP>(T(1), U[0]);
     T ke = T(0);
 #pragma unroll
     for (int d = 0; d < D; ++d) ke += U[1 + d] * U[1 + d];
@@ -93,16 +104,17 @@ __device__ __forceinline__ void flux_dir(const T* U, T gm1, int dir, T* F, T& p,
 // HLLC follows Toro, Spruce and Speares with Einfeldt wave-speed bounds built
 // from Roe averages; branch ties resolved as S_L >= 0 -> left, S* >= 0 -> left
 // star, S_R > 0 -> right star, else right.
-template <int D, typename T = double>
+// RCP: divisions as products with Newton-refined reciprocals (see dv).
+template <int D, typename T = double, bool RCP = false>
 __device__ __forceinline__ void riemann(const T* UL, const T* UR, int dir, int solver, T gamma, T* F)
 {
     constexpr int NV = D + 2;
     const T gm1 = gamma - T(1);
     T FL[NV], FR[NV], pL, pR, uL, uR;
-    flux_dir<D, T>(UL, gm1, dir, FL, pL, uL);
-    flux_dir<D, T>(UR, gm1, dir, FR, pR, uR);
+    flux_dir<D, T, RCP>(UL, gm1, dir, FL, pL, uL);
+    flux_dir<D, T, RCP>(UR, gm1, dir, FR, pR, uR);
     const T rL = UL[0], rR = UR[0];
-    const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+    const T cL = sqrt(dv<RCP>(gamma * pL, rL)), cR = sqrt(dv<RCP>(gamma * pR, rR));
     if (solver == 2) {
         const T s = fmax(fabs(uL) + cL, fabs(uR) + cR);
 #pragma unroll
@@ -110,12 +122,12 @@ __device__ __forceinline__ void riemann(const T* UL, const T* UR, int dir, int s
         return;
     }
     const T sL = sqrt(rL), sR = sqrt(rR);
-    const T isum = T(1) / (sL + sR);
-    const T HL = (UL[NV - 1] + pL) / rL, HR = (UR[NV - 1] + pR) / rR;
+    const T isum = dv<RCP>(T(1), sL + sR);
+    const T HL = dv<RCP>(UL[NV - 1] + pL, rL), HR = dv<RCP>(UR[NV - 1] + pR, rR);
     T q2 = T(0), utn = T(0);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const T ut = (UL[1 + d] / sL + UR[1 + d] / sR) * isum;
+        const T ut = (dv<RCP>(UL[1 + d], sL) + dv<RCP>(UR[1 + d], sR)) * isum;
         q2 += ut * ut;
         if (d == dir) utn = ut;
     }
@@ -131,14 +143,14 @@ __device__ __forceinline__ void riemann(const T* UL, const T* UR, int dir, int s
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] = FR[v];
         } else {
-            const T id = T(1) / (SR - SL);
+            const T id = dv<RCP>(T(1), SR - SL);
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) * id;
         }
         return;
     }
     const T mL = rL * (SL - uL), mR = rR * (SR - uR);
-    const T Ss = (pR - pL + mL * uL - mR * uR) / (mL - mR);
+    const T Ss = dv<RCP>(pR - pL + mL * uL - mR * uR, mL - mR);
     if (SL >= T(0)) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) F[v] = FL[v];
@@ -158,13 +170,13 @@ __device__ __forceinline__ void riemann(const T* UL, const T* UR, int dir, int s
     const T uk = left ? uL : uR;
     const T pk = left ? pL : pR;
     const T mk = left ? mL : mR;
-    const T f = mk / (Sk - Ss);
-    const T irk = T(1) / rk;
+    const T f = dv<RCP>(mk, Sk - Ss);
+    const T irk = dv<RCP>(T(1), rk);
     T Us[NV];
     Us[0] = f;
 #pragma unroll
     for (int d = 0; d < D; ++d) Us[1 + d] = f * (d == dir ? Ss : Uk[1 + d] * irk);
-    Us[NV - 1] = f * (Uk[NV - 1] * irk + (Ss - uk) * (Ss + pk / mk));
+    Us[NV - 1] = f * (Uk[NV - 1] * irk + (Ss - uk) * (Ss + dv<RCP>(pk, mk)));
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v] = Fk[v] + Sk * (Us[v] - Uk[v]);
 }
