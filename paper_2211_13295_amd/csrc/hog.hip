@@ -328,14 +328,17 @@ int enqueue_o2(hog_grid* g, double dt_user)
                          (D == 3 ? (L.n[1] + S::TY - 3) / (S::TY - 2) : 1) * ((L.n[D - 1] + a.zc - 1) / a.zc);
     {
         StageMark m(g, 2);
+        O2Taps tp;
+        tp.Q = static_cast<double*>(g->Q);
+        tp.R = L.R;
+        for (int d = 0; d < 3; ++d) { tp.F[d] = g->F[d]; tp.FB[d] = L.FB[d]; }
         auto launch = [&](auto kernel) {
-            kernel<<<xcd_blocks(nb), S::TX * S::TY, 0, s>>>(g->U[g->cur], g->U[g->cur ^ 1], L.pad, a, g->info,
-                                                           static_cast<double*>(g->Q), L.R, g->F[0], L.FB[0],
-                                                           g->F[1], L.FB[1], g->F[2], L.FB[2]);
+            kernel<<<xcd_blocks(nb), S::TX * S::TY, 0, s>>>(g->U[g->cur], g->U[g->cur ^ 1], L.pad, a, g->info, tp);
         };
-        if (g->cfg.riemann == HOG_HLLC) launch(k_o2_step<D, HOG_HLLC>);
-        else if (g->cfg.riemann == HOG_HLL) launch(k_o2_step<D, HOG_HLL>);
-        else launch(k_o2_step<D, HOG_RUSANOV>);
+        const bool taps = g->Q != nullptr;
+        if (g->cfg.riemann == HOG_HLLC) taps ? launch(k_o2_step<D, HOG_HLLC, true>) : launch(k_o2_step<D, HOG_HLLC, false>);
+        else if (g->cfg.riemann == HOG_HLL) taps ? launch(k_o2_step<D, HOG_HLL, true>) : launch(k_o2_step<D, HOG_HLL, false>);
+        else taps ? launch(k_o2_step<D, HOG_RUSANOV, true>) : launch(k_o2_step<D, HOG_RUSANOV, false>);
     }
     return launch_check("second-order step");
 }

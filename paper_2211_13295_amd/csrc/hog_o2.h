@@ -98,11 +98,18 @@ __device__ __forceinline__ bool o2_modes(const double* u, NB&& nb, const double*
     return ok;
 }
 
-template <int D, int SOLVER>
+// Debug taps of the step: modes of the predictor box and the face fluxes
+// (written only by the TAPS instantiation).
+struct O2Taps {
+    double* Q;
+    Box R;
+    double* F[3];
+    Box FB[3];
+};
+
+template <int D, int SOLVER, bool TAPS>
 __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ Uo, double* __restrict__ Un, Pad p,
-                                                 O2Args a, StepInfo* info, double* __restrict__ Q, Box R,
-                                                 double* __restrict__ Fx, Box FBx, double* __restrict__ Fy,
-                                                 Box FBy, double* __restrict__ Fz, Box FBz)
+                                                 O2Args a, StepInfo* info, O2Taps tp)
 {
     using Sh = O2Shape<D>;
     constexpr int TX = Sh::TX, TY = Sh::TY, NT = TX * TY, NV = D + 2;
@@ -166,10 +173,13 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
     double Um[NV], Uc[NV], Up[NV], Uq[NV], Rq[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) { Uq[v] = 0.0; Rq[v] = 0.0; }
+    const double* Uv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Uv[v] = Uo + v * p.vs;
     auto load = [&](double* dst, int x, int y, int m) {
         const long long g = gidx(x, y, m);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) dst[v] = Uo[v * p.vs + g];
+        for (int v = 0; v < NV; ++v) dst[v] = Uv[v][g];
     };
     // prologue: planes m0-2 .. m0 in registers, plane m0-1 in LDS
     load(Um, gx_own, gy_own, m0 - 2);
@@ -191,13 +201,17 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
     for (int v = 0; v < NV; ++v) { zp_prev[v] = 0.0; acc[v] = 0.0; }
     double smax = 0.0;
     unsigned long long nfb = 0;
-    const long long nR = box_size(R);
+    double* const Q = TAPS ? tp.Q : nullptr;
+    double* const Fx = TAPS ? tp.F[0] : nullptr;
+    double* const Fy = TAPS ? tp.F[1] : nullptr;
+    double* const Fz = TAPS ? tp.F[2] : nullptr;
+    const Box& R = tp.R;
+    const Box& FBx = tp.FB[0];
+    const Box& FBy = tp.FB[1];
+    const Box& FBz = tp.FB[2];
+    const long long nR = TAPS ? box_size(R) : 0;
 
     for (int m = m0 - 1; m <= m1; ++m) {
-        // own zone of plane m+2 for the next iteration; ring of plane m+1 for the
-        // LDS copy of that plane written after barrier B
-        if (m + 2 <= m1 + 1) load(Uq, gx_own, gy_own, m + 2);
-        if (tid < NRING) load(Rq, gx_ring, gy_ring, m + 1);
         __syncthreads();   // A: plane m complete in LDS
         const bool xy_plane = m >= m0 && m < m1;      // planes whose x / y faces are needed
         double S[D][NV], T[NV];
@@ -218,7 +232,7 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
                 if (live && own_x && own_y && m >= own_m_lo && m <= own_m_hi) ++nfb;
             }
         }
-        if (Q && live && own_x && own_y && m >= own_m_lo && m <= own_m_hi) {
+        if (TAPS && live && own_x && own_y && m >= own_m_lo && m <= own_m_hi) {
             const int i = ci, j = (D == 3) ? cj : m, k = (D == 3) ? m : 0;
             const long long r = box_index(R, i, j, k);
 #pragma unroll
@@ -264,7 +278,7 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
             if (ok) smax = fmax(smax, sp);
             else atomicMin(&info->bad, (unsigned long long)(((long long)k * n1 + j) * n0 + i));
         }
-        if (Fx && zface && inner) {
+        if (TAPS && zface && inner) {
             Box FB = (D == 3) ? FBz : FBy;
             double* Fm = (D == 3) ? Fz : Fy;
             const int i = ci, j = (D == 3) ? cj : m - 1, k = (D == 3) ? m - 1 : 0;
@@ -277,9 +291,13 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
 #pragma unroll
         for (int v = 0; v < NV; ++v) acc[v] = zface ? lam[D - 1] * Fzm[v] : 0.0;
         __syncthreads();   // B: face states visible; plane m no longer read
+        // own zone of plane m+2 for the next iteration (in flight during the
+        // Riemann solves); plane m+1 into LDS (the ring read here)
+        if (m + 2 <= m1 + 1) load(Uq, gx_own, gy_own, m + 2);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sU[v][own_l] = Up[v];
         if (tid < NRING) {
+            load(Rq, gx_ring, gy_ring, m + 1);
 #pragma unroll
             for (int v = 0; v < NV; ++v) sU[v][ring_l] = Rq[v];
         }
@@ -303,7 +321,7 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
             }
         }
         __syncthreads();   // C: -x / -y fluxes visible
-        if (Fx && xy_plane && inner) {
+        if (TAPS && xy_plane && inner) {
             const int i = ci, j = (D == 3) ? cj : m, k = (D == 3) ? m : 0;
             const long long nF = box_size(FBx);
             const long long f = box_index(FBx, i, j, k);   // face i + 1/2
