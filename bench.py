@@ -27,8 +27,10 @@ METRIC = "zone-updates/sec, 3D Euler WENO+ADER, FP64 vs FP32+learned gate at sta
 UNIT = "zone-updates/s"
 PEAK_FP64_VALU_TFLOPS = 78.6          # MI355X published FP64 vector peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_predictor_vortex3d_128.json")
+TRAFFIC_FILE_O2 = os.path.join(ROOT, "profiles", "traffic_o2_step_vortex3d_128.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2211_13295_amd", "csrc", f)
                   for f in ("hog_kernels.h", "hog_physics.h", "hog_tables.h")]
+KERNEL_SOURCES_O2 = KERNEL_SOURCES + [os.path.join(ROOT, "paper_2211_13295_amd", "csrc", "hog_o2.h")]
 
 
 def _binom(n, k):
@@ -129,23 +131,25 @@ def o2_flops(D, n, solver="hll"):
     return modes * zones_m + riem * faces + upd * n ** D
 
 
-def kernel_hash():
+def kernel_hash(sources=KERNEL_SOURCES):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_record():
-    """HBM bytes per predictor launch measured with rocprofv3 counters, if the
-    kernel sources have not changed since they were taken."""
+def traffic_record(second_order=False):
+    """HBM bytes per launch of the dominant kernel (the predictor, or the fused
+    second-order kernel) measured with rocprofv3 counters, if the kernel
+    sources have not changed since they were taken."""
+    path, src = (TRAFFIC_FILE_O2, KERNEL_SOURCES_O2) if second_order else (TRAFFIC_FILE, KERNEL_SOURCES)
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_hash") != kernel_hash():
+    if rec.get("kernel_hash") != kernel_hash(src):
         return None
     return rec.get("bytes_per_launch")
 
@@ -153,13 +157,18 @@ def traffic_record():
 PMC_COMMAND = ("export TMPDIR=/tmp; timeout -s KILL 240 rocprofv3 --pmc {ctr} --kernel-include-regex "
                "\"k_predict|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --steps 2 "
                "--warmup 0 --no-cpu-baseline --no-mixed --copy-calibration")
+PMC_COMMAND_O2 = ("export TMPDIR=/tmp; timeout -s KILL 240 rocprofv3 --pmc {ctr} --kernel-include-regex "
+                  "\"k_o2_step|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py "
+                  "--second-order --steps 3 --warmup 0 --no-cpu-baseline --copy-calibration")
 
 
-def write_traffic(fetch_csv, write_csv, n=128):
-    """Traffic record of the FP64 predictor from two rocprofv3 counter runs
-    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of this script with
-    --copy-calibration: each counter is scaled by what it reads for the plain
-    copy of 2^27 doubles (1 GiB read, 1 GiB written) in the same run."""
+def write_traffic(fetch_csv, write_csv, n=128, second_order=False):
+    """Traffic record of the FP64 predictor (or of the fused second-order
+    kernel) from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB
+    per dispatch) of this script with --copy-calibration: each counter is
+    scaled by what it reads for the plain copy of 2^27 doubles (1 GiB read,
+    1 GiB written) in the same run."""
+    kname = "k_o2_step<3" if second_order else "k_predict<3, 3, double>"
     import csv
     from collections import defaultdict
 
@@ -172,16 +181,35 @@ def write_traffic(fetch_csv, write_csv, n=128):
                     continue
                 acc[r["Dispatch_Id"]] += float(r["Counter_Value"])
                 names[r["Dispatch_Id"]] = r["Kernel_Name"]
-        pred = [v * 1024 for d, v in acc.items() if "k_predict<3, 3, double>" in names[d]]
+        pred = [v * 1024 for d, v in acc.items() if kname in names[d]]
         copy = [v * 1024 for d, v in acc.items() if "MulFunctor" in names[d]]   # the x * 1.0 copies
         if not pred or not copy:
-            raise SystemExit(f"{path}: no predictor or copy dispatch with {counter}")
+            raise SystemExit(f"{path}: no {kname} or copy dispatch with {counter}")
         return sum(pred) / len(pred), sum(copy) / len(copy)
 
     gib = float(1 << 30)
     fetch, fcopy = per_dispatch(fetch_csv, "FETCH_SIZE")
     write, wcopy = per_dispatch(write_csv, "WRITE_SIZE")
     fs, ws = gib / fcopy, gib / wcopy
+    if second_order:
+        rec = {
+            "kernel": "k_o2_step<3, HLL> (fused second-order step, FP64)",
+            "workload": f"3D vortex + density modes, {n}^3, order 2, HLL",
+            "kernel_hash": kernel_hash(KERNEL_SOURCES_O2),
+            "bytes_per_launch": fetch * fs + write * ws,
+            "fetch_bytes_per_launch": fetch * fs,
+            "write_bytes_per_launch": write * ws,
+            "fetch_scale": fs,
+            "write_scale": ws,
+            "algorithmic_bytes_per_launch": n ** 3 * 5 * 8 * 2,
+            "commands": [PMC_COMMAND_O2.format(ctr="FETCH_SIZE", tag="fetch"),
+                         PMC_COMMAND_O2.format(ctr="WRITE_SIZE", tag="write")],
+            "calibration": "plain elementwise copy of 2^27 doubles (1 GiB read + 1 GiB written) in the same runs",
+        }
+        with open(TRAFFIC_FILE_O2, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec, indent=1))
+        return
     zones = (n + 2) ** 3
     rec = {
         "kernel": "k_predict<3,3> (FP64)",
@@ -265,7 +293,7 @@ def second_order_line(hog, torch, args):
                    "zones": zones, "order": 2, "riemann": "hll", "precision": "fp64"},
         "roofline": {"bound": "alu", "kernel": "k_o2_step (fused second-order step)", "achieved": achieved,
                      "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_TFLOPS,
-                     "traffic": None, "alg_flops_per_launch": flops, "alg_flops_per_zone": flops / zones,
+                     "traffic": traffic_record(second_order=True), "alg_flops_per_launch": flops, "alg_flops_per_zone": flops / zones,
                      "avg_launch_ms": avg_s * 1e3,
                      "hbm": {"alg_bytes_per_launch": hbm_bytes, "achieved_GBps": hbm_bytes / avg_s / 1e9,
                              "peak_GBps": 8000.0, "frac": hbm_bytes / avg_s / 8e12}},
@@ -545,7 +573,7 @@ def main():
                     help="write the predictor traffic record from two rocprofv3 counter files and exit")
     args = ap.parse_args()
     if args.traffic_from:
-        write_traffic(*args.traffic_from)
+        write_traffic(*args.traffic_from, second_order=args.second_order)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU path (halo exchange and a min "
@@ -564,13 +592,6 @@ def main():
         steps = 100 if args.gate_ablation == "multiblast256" else 200
         print(json.dumps(gate_ablation(hog, torch, args.gate_ablation, steps, 20)), flush=True)
         return
-    if args.second_order:
-        print(json.dumps(second_order_line(hog, torch, args)), flush=True)
-        return
-    if args.shock_workload:
-        steps = 100 if args.shock_workload == "multiblast256" else 200
-        print(json.dumps(shock_workload(hog, torch, args.shock_workload, steps, 20)), flush=True)
-        return
     if args.copy_calibration:
         x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
@@ -579,6 +600,13 @@ def main():
         torch.cuda.synchronize()
         print(f"copy calibration: 3 launches of {x.numel() * 8} bytes read + written", flush=True)
         del x, y
+    if args.second_order:
+        print(json.dumps(second_order_line(hog, torch, args)), flush=True)
+        return
+    if args.shock_workload:
+        steps = 100 if args.shock_workload == "multiblast256" else 200
+        print(json.dumps(shock_workload(hog, torch, args.shock_workload, steps, 20)), flush=True)
+        return
     n, order = args.n, args.order
     pb = icgen.vortex3d_perturbed(n=n, seed=2)
     g = hog.Grid.from_problem(pb, order)
