@@ -21,6 +21,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 RIEMANN = {"hllc": 0, "hll": 1, "rusanov": 2}
+STEPPER = {"ader": 0, "rk2": 2, "rk3": 3, "rk4": 4}
 BC = {"periodic": 0, "outflow": 1}
 
 
@@ -42,6 +43,7 @@ class OCfg(C.Structure):
         ("gamma", C.c_double), ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
         ("cfl", C.c_double), ("weno_eps", C.c_double),
         ("g3", C.c_double * 3), ("g4", C.c_double * 4),
+        ("stepper", C.c_int),
     ]
 
 
@@ -95,6 +97,10 @@ def lib():
             getattr(L, f).argtypes = [C.c_int, C.c_int]
             getattr(L, f).restype = C.c_double
         L.oracle_gauss.argtypes = [C.c_int, dp, dp]
+        L.oracle_rk_table.argtypes = [C.c_int, C.c_void_p, C.c_void_p]
+        L.oracle_rk_table.restype = C.c_int
+        L.oracle_rk_operator.argtypes = [cp, dp, C.c_double, dp]
+        L.oracle_rk_operator.restype = C.c_int
         L.oracle_mc.argtypes = [C.c_double, C.c_double, C.c_double]
         L.oracle_mc.restype = C.c_double
         _lib = L
@@ -102,7 +108,7 @@ def lib():
 
 
 def make_cfg(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("periodic",) * 3,
-             linear_weno=False, eps=DEFAULT_EPS, g3=DEFAULT_G3, g4=DEFAULT_G4, positivity=True):
+             linear_weno=False, eps=DEFAULT_EPS, g3=DEFAULT_G3, g4=DEFAULT_G4, positivity=True, stepper="ader"):
     c = OCfg()
     c.ndim = ndim
     c.nx, c.ny, c.nz = int(n[0]), int(n[1]), int(n[2]) if ndim == 3 else 1
@@ -121,6 +127,7 @@ def make_cfg(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("periodi
         c.g3[i] = g3[i]
     for i in range(4):
         c.g4[i] = g4[i]
+    c.stepper = STEPPER[stepper] if isinstance(stepper, str) else int(stepper)
     return c
 
 
@@ -275,6 +282,25 @@ def riemann(cfg, d, UL, UR):
 def phys_flux(cfg, d, U):
     out = np.zeros(cfg.ndim + 2)
     lib().oracle_phys_flux(C.byref(cfg), d, _state(U), out)
+    return out
+
+
+def rk_table(stepper):
+    """Shu-Osher coefficients of a Runge-Kutta stepper: list of (i, k, alpha, beta)."""
+    st = STEPPER[stepper] if isinstance(stepper, str) else int(stepper)
+    n = lib().oracle_rk_table(st, None, None)
+    ik = (C.c_int * (2 * n))()
+    ab = (C.c_double * (2 * n))()
+    lib().oracle_rk_table(st, ik, ab)
+    return [(ik[2 * s], ik[2 * s + 1], ab[2 * s], ab[2 * s + 1]) for s in range(n)]
+
+
+def rk_operator(cfg, U, dt):
+    """dt L(U) of the method-of-lines operator (interior SoA)."""
+    U = _state(U)
+    out = np.empty_like(U)
+    if lib().oracle_rk_operator(C.byref(cfg), U, float(dt), out) != 0:
+        raise MemoryError("oracle_rk_operator failed")
     return out
 
 

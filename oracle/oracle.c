@@ -59,6 +59,7 @@ typedef struct {
     double weno_eps;   /* epsilon in omega~ = gamma_k / (eps + IS_k)^2 */
     double g3[3];      /* O3 linear weights for the L, C, R quadratics */
     double g4[4];      /* O4 linear weights for the H (cubic), L, C, R members */
+    int stepper;       /* 0 ADER (the predictor / Hancock step); 2, 3, 4: SSP-RK with 2, 3, 5 stages */
 } ocfg;
 
 /* ------------------------------------------------------------------------ */
@@ -884,6 +885,229 @@ static int o2_stage_modes(const ocfg *c, const double *U, double dt, double *Wou
 }
 
 /* ------------------------------------------------------------------------ */
+/* Runge-Kutta time stepping (Sec. I.1; Sec. III.1, Table IV)                */
+/* ------------------------------------------------------------------------ */
+/* The paper compares its ADER step with multi-stage Runge-Kutta schemes built
+ * from the same reconstruction and Riemann solver: two stages at second order,
+ * three at third, five at fourth.  They are read as the strong-stability-
+ * preserving schemes of that shape: SSP-RK(2,2) and SSP-RK(3,3) of Shu and
+ * Osher, and SSP-RK(5,4) of Spiteri and Ruuth, in Shu-Osher form
+ *   u(i) = sum_{k<i} ( alpha_ik u(k) + beta_ik dt L(u(k)) ),  u(0) = U^n,
+ * with the published coefficients (the fourth-order conditions are checked in
+ * the tests).  L is the method-of-lines operator: the spatial polynomial of
+ * every zone (WENO at third/fourth order, mean + MC slopes at second order),
+ * the Riemann solver at the face points in space only (2-point Gauss per
+ * tangential axis; the face centre at second order), and the flux
+ * difference. */
+typedef struct { int i, k; double alpha, beta; } rk_term;
+
+static int rk_table(int stepper, const rk_term **t)
+{
+    static const rk_term rk2[] = {{1, 0, 1.0, 1.0}, {2, 0, 0.5, 0.0}, {2, 1, 0.5, 0.5}};
+    static const rk_term rk3[] = {{1, 0, 1.0, 1.0},
+                                  {2, 0, 0.75, 0.0}, {2, 1, 0.25, 0.25},
+                                  {3, 0, 1.0 / 3.0, 0.0}, {3, 2, 2.0 / 3.0, 2.0 / 3.0}};
+    static const rk_term rk54[] = {{1, 0, 1.0, 0.391752226571890},
+                                   {2, 0, 0.444370493651235, 0.0}, {2, 1, 0.555629506348765, 0.368410593050371},
+                                   {3, 0, 0.620101851488403, 0.0}, {3, 2, 0.379898148511597, 0.251891774271694},
+                                   {4, 0, 0.178079954393132, 0.0}, {4, 3, 0.821920045606868, 0.544974750228521},
+                                   {5, 2, 0.517231671970585, 0.0}, {5, 3, 0.096059710526147, 0.063692468666290},
+                                   {5, 4, 0.386708617503269, 0.226007483236906}};
+    if (stepper == 2) { *t = rk2; return (int)(sizeof rk2 / sizeof rk2[0]); }
+    if (stepper == 3) { *t = rk3; return (int)(sizeof rk3 / sizeof rk3[0]); }
+    if (stepper == 4) { *t = rk54; return (int)(sizeof rk54 / sizeof rk54[0]); }
+    return 0;
+}
+static int rk_stages(int stepper) { return stepper == 2 ? 2 : (stepper == 3 ? 3 : (stepper == 4 ? 5 : 0)); }
+
+/* Coefficient table for the tests: n terms of (i, k, alpha, beta). */
+int oracle_rk_table(int stepper, int *ik, double *ab)
+{
+    const rk_term *t;
+    int n = rk_table(stepper, &t);
+    for (int s = 0; s < n && ik; ++s) {
+        ik[2 * s] = t[s].i; ik[2 * s + 1] = t[s].k;
+        ab[2 * s] = t[s].alpha; ab[2 * s + 1] = t[s].beta;
+    }
+    return n;
+}
+
+/* Spatial modes W [1 + nd or ms][nv] (st_modes order, e = 0 block) of zone
+ * (i, j, k) for the method of lines: WENO at third/fourth order, the mean and
+ * MC slopes of Fig. 3 at second order.  With the positivity option a zone whose
+ * polynomial is inadmissible at one of its face points keeps only its mean.
+ * Returns 1 for such a zone. */
+static int rk_zone_modes(const ocfg *c, const grid_t *g, const double *P, int i, int j, int k, double *W,
+                         int *ms_out)
+{
+    int nd = g->nd, nv = g->nv, ms;
+    mode4 m[MAXST];
+    if (c->order == 2) {
+        ms = 1 + nd;
+        st_modes(nd, 1, m);
+        for (int v = 0; v < nv; ++v) W[v] = P[v * g->vs + pidx(g, i, j, k)];
+        for (int d = 0; d < nd; ++d) {
+            int o[3] = {0, 0, 0};
+            o[d] = 1;
+            for (int v = 0; v < nv; ++v) {
+                double lo = P[v * g->vs + pidx(g, i - o[0], j - o[1], k - o[2])];
+                double hi = P[v * g->vs + pidx(g, i + o[0], j + o[1], k + o[2])];
+                W[(1 + d) * nv + v] = oracle_mc(hi - W[v], W[v] - lo, o2_cfac(v));
+            }
+        }
+    } else {
+        double blk[MAXV * 125];
+        unsigned char fl[25];
+        int nst = st_modes(nd, c->order - 1, m);
+        ms = 0;
+        for (int t = 0; t < nst; ++t) ms += (m[t].e == 0);
+        gather_block(g, P, i, j, k, blk);
+        memset(fl, 0, sizeof fl);
+        oracle_recon_block_ex(c, blk, W, fl, NULL);
+    }
+    *ms_out = ms;
+    if (!c->positivity) return 0;
+    double s = 0.5 / sqrt(3.0);
+    int npt = (c->order == 2) ? 1 : (nd == 3 ? 4 : 2);
+    int bad = 0;
+    for (int dir = 0; dir < nd && !bad; ++dir)
+        for (int side = 0; side < 2 && !bad; ++side)
+            for (int pt = 0; pt < npt && !bad; ++pt) {
+                double x[3] = {0, 0, 0}, U[MAXV];
+                int t1 = (dir == 0) ? 1 : 0, t2 = (nd == 3) ? ((dir == 2) ? 1 : 2) : -1;
+                x[dir] = side ? 0.5 : -0.5;
+                if (c->order != 2) {
+                    x[t1] = (pt & 1) ? s : -s;
+                    if (t2 >= 0) x[t2] = (pt & 2) ? s : -s;
+                }
+                eval_modes(nv, ms, m, W, x[0], x[1], x[2], 0.0, U);
+                if (!admissible(c, U)) bad = 1;
+            }
+    if (!bad) return 0;
+    for (int t = nv; t < ms * nv; ++t) W[t] = 0.0;
+    return 1;
+}
+
+/* Face flux between zones Wa (lower) and Wb along dir in space only: the
+ * Riemann solver at 2-point Gauss points of the tangential axes (weights 1/2
+ * each, first tangential axis outer), or at the face centre at second order. */
+static void rk_face_flux(const ocfg *c, int dir, const double *Wa, const double *Wb, int ms, double *F)
+{
+    int nd = c->ndim, nv = nd + 2;
+    mode4 m[MAXST];
+    st_modes(nd, (c->order == 2) ? 1 : c->order - 1, m);
+    double s = 0.5 / sqrt(3.0);
+    int t1 = (dir == 0) ? 1 : 0, t2 = (nd == 3) ? ((dir == 2) ? 1 : 2) : -1;
+    int n1 = (c->order == 2) ? 1 : 2, n2 = (c->order == 2 || nd == 2) ? 1 : 2;
+    double w = 1.0 / (n1 * n2);
+    for (int v = 0; v < nv; ++v) F[v] = 0.0;
+    for (int a1 = 0; a1 < n1; ++a1)
+        for (int a2 = 0; a2 < n2; ++a2) {
+            double xl[3] = {0, 0, 0}, xr[3] = {0, 0, 0}, UL[MAXV], UR[MAXV], Fp[MAXV];
+            xl[dir] = 0.5;
+            xr[dir] = -0.5;
+            if (n1 == 2) xl[t1] = xr[t1] = a1 ? s : -s;
+            if (n2 == 2) xl[t2] = xr[t2] = a2 ? s : -s;
+            eval_modes(nv, ms, m, Wa, xl[0], xl[1], xl[2], 0.0, UL);
+            eval_modes(nv, ms, m, Wb, xr[0], xr[1], xr[2], 0.0, UR);
+            oracle_riemann(c, dir, UL, UR, Fp);
+            for (int v = 0; v < nv; ++v) F[v] += w * Fp[v];
+        }
+}
+
+/* dU = dt L(U) = -dt sum_d (F_d(+) - F_d(-)) / dx_d on the interior. */
+static int rk_operator(const ocfg *c, const double *U, double dt, double *dU, long long *ntroubled)
+{
+    grid_t g;
+    grid_init(c, &g);
+    int nd = g.nd, nv = g.nv;
+    double h[3] = {c->dx, c->dy, c->dz};
+    double *P = make_padded(c, &g, U);
+    if (!P) return -1;
+    int e[3] = {g.n[0] + 2, g.n[1] + 2, (nd == 3) ? g.n[2] + 2 : 1};
+    size_t ne = (size_t)e[0] * e[1] * e[2];
+    size_t ws = (size_t)MAXST * nv;
+    double *Wz = (double *)malloc(sizeof(double) * ne * ws);
+    if (!Wz) { free(P); return -1; }
+    int o3 = (nd == 3) ? 1 : 0, ms = 1;
+    long long nbad = 0;
+#pragma omp parallel for schedule(dynamic, 1) collapse(2) reduction(+ : nbad) reduction(max : ms)
+    for (int k = 0; k < e[2]; ++k)
+        for (int j = 0; j < e[1]; ++j)
+            for (int i = 0; i < e[0]; ++i) {
+                int msz;
+                nbad += rk_zone_modes(c, &g, P, i - 1, j - 1, k - o3, Wz + (((size_t)k * e[1] + j) * e[0] + i) * ws,
+                                      &msz);
+                if (msz > ms) ms = msz;
+            }
+    if (ntroubled) *ntroubled += nbad;
+#define WAT(i, j, k) (Wz + (((size_t)((k) + o3) * e[1] + ((j) + 1)) * e[0] + ((i) + 1)) * ws)
+    size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+#pragma omp parallel for schedule(static) collapse(2)
+    for (int k = 0; k < g.n[2]; ++k)
+        for (int j = 0; j < g.n[1]; ++j)
+            for (int i = 0; i < g.n[0]; ++i) {
+                size_t z = ((size_t)k * g.n[1] + j) * g.n[0] + i;
+                double du[MAXV] = {0};
+                for (int d = 0; d < nd; ++d) {
+                    int o[3] = {0, 0, 0};
+                    o[d] = 1;
+                    double Fm[MAXV], Fp[MAXV];
+                    rk_face_flux(c, d, WAT(i - o[0], j - o[1], k - o[2]), WAT(i, j, k), ms, Fm);
+                    rk_face_flux(c, d, WAT(i, j, k), WAT(i + o[0], j + o[1], k + o[2]), ms, Fp);
+                    for (int v = 0; v < nv; ++v) du[v] -= dt * (Fp[v] - Fm[v]) / h[d];
+                }
+                for (int v = 0; v < nv; ++v) dU[v * N + z] = du[v];
+            }
+#undef WAT
+    free(Wz);
+    free(P);
+    return 0;
+}
+
+/* One Runge-Kutta step of the whole grid; *ntroubled receives the fallback
+ * zones summed over the stages. */
+static int rk_step(const ocfg *c, const double *U, double dt, double *Unew, long long *ntroubled)
+{
+    const rk_term *t;
+    int nt = rk_table(c->stepper, &t), s = rk_stages(c->stepper);
+    if (!nt) return -2;
+    int nd = c->ndim, nv = nd + 2;
+    size_t N = (size_t)c->nx * c->ny * ((nd == 3) ? c->nz : 1), nn = N * nv;
+    double *u = (double *)malloc(sizeof(double) * nn * (s + 1));   /* u(0) .. u(s) */
+    double *L = (double *)malloc(sizeof(double) * nn * s);         /* dt L(u(k)) */
+    if (!u || !L) { free(u); free(L); return -1; }
+    memcpy(u, U, sizeof(double) * nn);
+    *ntroubled = 0;
+    for (int i = 1; i <= s; ++i) {
+        if (rk_operator(c, u + (size_t)(i - 1) * nn, dt, L + (size_t)(i - 1) * nn, ntroubled)) {
+            free(u); free(L); return -1;
+        }
+        double *ui = u + (size_t)i * nn;
+        for (size_t q = 0; q < nn; ++q) ui[q] = 0.0;
+        for (int r = 0; r < nt; ++r) {
+            if (t[r].i != i) continue;
+            const double *uk = u + (size_t)t[r].k * nn, *Lk = L + (size_t)t[r].k * nn;
+            for (size_t q = 0; q < nn; ++q) {
+                ui[q] += t[r].alpha * uk[q];
+                if (t[r].beta != 0.0) ui[q] += t[r].beta * Lk[q];
+            }
+        }
+    }
+    memcpy(Unew, u + (size_t)s * nn, sizeof(double) * nn);
+    free(u);
+    free(L);
+    return 0;
+}
+
+/* dt L(U) for the tests (method-of-lines operator of the configured order). */
+int oracle_rk_operator(const ocfg *c, const double *U, double dt, double *dU)
+{
+    long long n = 0;
+    return rk_operator(c, U, dt, dU, &n);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Public entry points                                                       */
 /* ------------------------------------------------------------------------ */
 /* CFL time step of a state (interior SoA): dt = cfl / max_zones sum_d
@@ -930,6 +1154,7 @@ int oracle_step_count(const ocfg *c, const double *U, double dt, double *Unew, l
 int oracle_step_gated(const ocfg *c, const double *U, double dt, const unsigned char *gate, double *Unew,
                       long long *ntroubled)
 {
+    if (c->stepper != 0) return gate ? -2 : rk_step(c, U, dt, Unew, ntroubled);
     if (c->order == 2) return gate ? -2 : o2_step(c, U, dt, Unew, ntroubled);
     grid_t g;
     grid_init(c, &g);
@@ -986,6 +1211,7 @@ int oracle_step_gated(const ocfg *c, const double *U, double dt, const unsigned 
  * spot checks of large grids).  ijk: nlist triples; out: [nlist][nv]. */
 int oracle_step_zones(const ocfg *c, const double *U, double dt, int nlist, const int *ijk, double *out)
 {
+    if (c->stepper != 0) return -2;   /* a Runge-Kutta step is not local to a zone's stencil */
     if (c->order == 2) return o2_step_zones(c, U, dt, nlist, ijk, out);
     grid_t g;
     grid_init(c, &g);
@@ -1057,6 +1283,7 @@ int oracle_run(const ocfg *c, double *U, int nsteps, double t_end, double *t_out
  * modes q [zone][nst][nv] of every interior zone (ignoring zones beyond). */
 int oracle_stage_modes(const ocfg *c, const double *U, double dt, double *Wout, double *qout)
 {
+    if (c->stepper != 0) return -2;
     if (c->order == 2) return o2_stage_modes(c, U, dt, Wout, qout);
     grid_t g;
     grid_init(c, &g);
