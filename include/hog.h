@@ -65,6 +65,10 @@ enum { HOG_HLLC = 0, HOG_HLL = 1, HOG_RUSANOV = 2 };   /* Riemann solver */
  * nonlinear weights, the face-flux Gauss sum, the conservative update and the
  * CFL reduction in FP64.  The state is FP64 on both paths. */
 enum { HOG_FP64 = 0, HOG_MIXED = 1 };
+/* Time stepping (hog_config.stepper).  The Runge-Kutta schemes are the
+ * strong-stability-preserving ones in Shu-Osher form: SSP-RK(2,2) and
+ * SSP-RK(3,3) of Shu and Osher, SSP-RK(5,4) of Spiteri and Ruuth. */
+enum { HOG_ADER = 0, HOG_SSPRK2 = 2, HOG_SSPRK3 = 3, HOG_SSPRK54 = 4 };
 enum { HOG_SOA = 0, HOG_AOS = 1 };                     /* state layouts */
 enum { HOG_HOST = 0, HOG_DEVICE = 1 };                 /* where a user buffer lives */
 
@@ -101,7 +105,12 @@ typedef struct hog_config {
                             falls back to its zone mean (first order) for that step;
                             at order 2 the points checked are the face-centre values
                             U +- S_d/2 and the face states U +- S_d/2 + U5/2 */
-    int reserved[3];     /* must be 0 */
+    int stepper;         /* HOG_ADER (0): the one-step ADER predictor-corrector (at order 2
+                            the Hancock step of Fig. 4); HOG_SSPRK2 / HOG_SSPRK3 /
+                            HOG_SSPRK54: Runge-Kutta with 2, 3 or 5 stages (Table IV), each
+                            stage the same reconstruction and Riemann solver with
+                            face points in space only; FP64, no debug taps, no gate */
+    int reserved[2];     /* must be 0 */
     double gamma;        /* ratio of specific heats, > 1 */
     double dx, dy, dz;   /* zone widths (dz ignored in 2D), > 0 */
     double cfl;          /* CFL number of hog_compute_dt / dt_next, in (0, 1] */

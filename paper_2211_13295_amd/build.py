@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhog.so")
 SOURCES = [os.path.join(HERE, "csrc", "hog.hip")]
 HEADERS = [os.path.join(HERE, "csrc", f)
-           for f in ("hog_kernels.h", "hog_physics.h", "hog_tables.h", "hog_gate.h", "hog_o2.h")] + [
+           for f in ("hog_kernels.h", "hog_physics.h", "hog_tables.h", "hog_gate.h", "hog_o2.h", "hog_rk.h")] + [
     os.path.join(ROOT, "include", "hog.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -15,6 +15,7 @@
 #include "hog_kernels.h"
 #include "hog_gate.h"
 #include "hog_o2.h"
+#include "hog_rk.h"
 
 using namespace hog;
 
@@ -51,6 +52,9 @@ struct Plan {
     // byte offsets in the workspace
     size_t off_info, off_U[2], off_A, off_B, off_W, off_FP, off_F[3], off_Q, off_stage;
     size_t off_gate, off_flags, off_logits, total;
+    // Runge-Kutta: stage states u(1) .. u(s-1) (padded) and dt L(u(k)) (interior)
+    int nstages;
+    size_t off_S[6], off_L[6];
 };
 
 int nmodes(int d, int p) { int r = 1; for (int i = 1; i <= d; ++i) r = r * (p + i) / i; return r; }
@@ -71,8 +75,11 @@ int check_cfg(const hog_config* c)
         return fail(HOG_EINVAL, "precision %d not supported", c->precision);
     if (c->precision == HOG_MIXED && c->debug)
         return fail(HOG_EINVAL, "space-time mode taps are kept on the FP64 path only");
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (c->reserved[i] != 0) return fail(HOG_EINVAL, "reserved fields must be 0");
+    if (c->stepper != HOG_ADER && !rk_nstages(c->stepper)) return fail(HOG_EINVAL, "unknown stepper %d", c->stepper);
+    if (c->stepper != HOG_ADER && (c->precision != HOG_FP64 || c->debug))
+        return fail(HOG_EINVAL, "Runge-Kutta stepping runs on the FP64 path without debug taps");
     if (c->positivity != 0 && c->positivity != 1) return fail(HOG_EINVAL, "positivity must be 0 or 1");
     if (!(c->gamma > 1.0) || !std::isfinite(c->gamma)) return fail(HOG_EINVAL, "gamma must be > 1");
     const double h[3] = {c->dx, c->dy, c->dz};
@@ -144,6 +151,10 @@ void plan(const hog_config* c, Plan* P)
         P->off_F[d] = (d < nd && (!o2 || c->debug)) ? take(sizeof(double) * nv * box_size(P->FB[d])) : 0;
     P->off_Q = c->debug ? take(sizeof(double) * P->mst * nv * box_size(P->R)) : 0;
     P->off_stage = take(sizeof(double) * nv * box_size(P->I));
+    P->nstages = rk_nstages(c->stepper);
+    for (int k = 0; k < 6; ++k) { P->off_S[k] = 0; P->off_L[k] = 0; }
+    for (int k = 1; k < P->nstages; ++k) P->off_S[k] = take(sizeof(double) * nv * P->pad.vs);
+    for (int k = 0; k < P->nstages; ++k) P->off_L[k] = take(sizeof(double) * nv * box_size(P->I));
     P->off_gate = take(nd == 3 ? sizeof(GateParams<3>) : sizeof(GateParams<2>));
     P->off_flags = take(box_size(P->I));
     P->off_logits = take(sizeof(float) * box_size(P->I));
@@ -168,6 +179,7 @@ struct hog_grid {
     double* U[2];
     void *A, *B, *W, *FP, *Q;     // element type: double (FP64) or float (mixed)
     double *F[3], *stage;
+    double *S[6], *Lb[6];          // Runge-Kutta stage states and dt L buffers
     // learned gate (device copy of the parameters, per-zone flags and logits);
     // gate_on: flags are used by the steps; gate_fixed: they were set by the
     // caller (no inference); gate_net: a network is loaded
@@ -333,18 +345,127 @@ int enqueue_o2(hog_grid* g, double dt_user)
         tp.R = L.R;
         for (int d = 0; d < 3; ++d) { tp.F[d] = g->F[d]; tp.FB[d] = L.FB[d]; }
         auto launch = [&](auto kernel) {
-            kernel<<<xcd_blocks(nb), S::TX * S::TY, 0, s>>>(g->U[g->cur], g->U[g->cur ^ 1], L.pad, a, g->info, tp);
+            kernel<<<xcd_blocks(nb), S::TX * S::TY, 0, s>>>(g->U[g->cur], g->U[g->cur ^ 1], L.pad, a, g->info, tp,
+                                                           nullptr);
         };
         const bool taps = g->Q != nullptr;
-        if (g->cfg.riemann == HOG_HLLC) taps ? launch(k_o2_step<D, HOG_HLLC, true>) : launch(k_o2_step<D, HOG_HLLC, false>);
-        else if (g->cfg.riemann == HOG_HLL) taps ? launch(k_o2_step<D, HOG_HLL, true>) : launch(k_o2_step<D, HOG_HLL, false>);
-        else taps ? launch(k_o2_step<D, HOG_RUSANOV, true>) : launch(k_o2_step<D, HOG_RUSANOV, false>);
+        if (g->cfg.riemann == HOG_HLLC)
+            taps ? launch(k_o2_step<D, HOG_HLLC, true, false>) : launch(k_o2_step<D, HOG_HLLC, false, false>);
+        else if (g->cfg.riemann == HOG_HLL)
+            taps ? launch(k_o2_step<D, HOG_HLL, true, false>) : launch(k_o2_step<D, HOG_HLL, false, false>);
+        else taps ? launch(k_o2_step<D, HOG_RUSANOV, true, false>) : launch(k_o2_step<D, HOG_RUSANOV, false, false>);
     }
     return launch_check("second-order step");
 }
 
+// Runge-Kutta step: per stage, dt L of the previous stage state (reconstruction,
+// face points, Riemann solver; at second order the fused kernel) and the
+// Shu-Osher combination; the last stage writes the other state buffer and the
+// CFL reduction of the new state.
+template <int D, int P>
+int enqueue_rk(hog_grid* g, double dt_user)
+{
+    const Plan& L = g->P;
+    hipStream_t s = g->stream;
+    const double* h = g->h;
+    const int st = g->cfg.stepper, ns = L.nstages;
+    const RkRow* rows;
+    const int nrows = rk_rows(st, &rows);
+    k_begin_step<<<1, 1, 0, s>>>(g->info, dt_user, g->cfg.cfl, h[0], h[1], h[2]);
+    auto state = [&](int k) -> double* { return k == 0 ? g->U[g->cur] : (k == ns ? g->U[g->cur ^ 1] : g->S[k]); };
+    for (int i = 1; i <= ns; ++i) {
+        double* src = state(i - 1);
+        const bool keep = rk_keep_L(st, i - 1);
+        if constexpr (P == 1) {
+            using S = O2Shape<D>;
+            O2Args a;
+            for (int d = 0; d < 3; ++d) { a.n[d] = L.n[d]; a.bc[d] = g->cfg.bc[d]; a.ih[d] = 1.0 / h[d]; }
+            a.zc = o2_chunk<D>(L, g->cus);
+            a.positivity = g->cfg.positivity;
+            a.gamma = g->cfg.gamma;
+            const long long nb = (long long)((L.n[0] + S::TX - 3) / (S::TX - 2)) *
+                                 (D == 3 ? (L.n[1] + S::TY - 3) / (S::TY - 2) : 1) *
+                                 ((L.n[D - 1] + a.zc - 1) / a.zc);
+            O2Taps tp;
+            std::memset(&tp, 0, sizeof tp);
+            StageMark m(g, 2);
+            auto launch = [&](auto kernel) {
+                kernel<<<xcd_blocks(nb), S::TX * S::TY, 0, s>>>(src, nullptr, L.pad, a, g->info, tp, g->Lb[i - 1]);
+            };
+            if (g->cfg.riemann == HOG_HLLC) launch(k_o2_step<D, HOG_HLLC, false, true>);
+            else if (g->cfg.riemann == HOG_HLL) launch(k_o2_step<D, HOG_HLL, false, true>);
+            else launch(k_o2_step<D, HOG_RUSANOV, false, true>);
+        } else {
+            double* A = static_cast<double*>(g->A);
+            double* B = static_cast<double*>(g->B);
+            double* W = static_cast<double*>(g->W);
+            double* FPa = static_cast<double*>(g->FP);
+            {
+                StageMark m(g, 0);
+                const long long npad = (long long)L.pad.np[0] * L.pad.np[1] * L.pad.np[2];
+                k_ghost<D><<<nblocks(npad, 256), 256, 0, s>>>(src, L.pad, L.n[0], L.n[1], L.n[2], g->cfg.bc[0],
+                                                               g->cfg.bc[1], g->cfg.bc[2]);
+            }
+            {
+                StageMark m(g, 1);
+                k_recon_x<D, P, double><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(src, L.pad, L.AX, A, g->wa,
+                                                                                     nullptr, L.I);
+                k_recon_y<D, P, double><<<nblocks(recon_y_threads<D, P>(L.BY), 256), 256, 0, s>>>(
+                    A, L.AX, L.BY, B, g->wa, nullptr, L.I);
+                if constexpr (D == 3)
+                    k_recon_z<P, double><<<nblocks(recon_z_threads<P>(L.R), 256), 256, 0, s>>>(B, L.BY, L.R, W, g->wa,
+                                                                                               nullptr, L.I);
+            }
+            {
+                StageMark m(g, 2);
+                k_face_points<D, P><<<nblocks(box_size(L.R), 256), 256, 0, s>>>(
+                    W, L.R, g->info, g->cfg.gamma, g->cfg.positivity, FPa);
+            }
+            {
+                StageMark m(g, 3);
+                for (int d = 0; d < D; ++d)
+                    k_riemann<D, double, (1 << (D - 1))><<<nblocks(box_size(L.FB[d]), 256), 256, 0, s>>>(
+                        FPa, L.R, L.FB[d], d, g->cfg.riemann, g->cfg.gamma, g->F[d]);
+            }
+        }
+        RkStage sg;
+        sg.n = 0;
+        for (int r = 0; r < nrows; ++r) {
+            if (rows[r].i != i) continue;
+            sg.src[sg.n] = state(rows[r].k);
+            sg.padded[sg.n] = 1;
+            sg.coef[sg.n] = rows[r].alpha;
+            ++sg.n;
+            if (rows[r].beta != 0.0) {
+                sg.src[sg.n] = (rows[r].k == i - 1) ? nullptr : g->Lb[rows[r].k];
+                sg.padded[sg.n] = 0;
+                sg.coef[sg.n] = rows[r].beta;
+                ++sg.n;
+            }
+        }
+        StageMark m(g, 4);
+        const bool o2 = (P == 1);
+        k_rk_combine<D><<<nblocks(box_size(L.I), 256), 256, 0, s>>>(
+            L.pad, L.I, g->F[0], L.FB[0], g->F[1], L.FB[1], g->F[2], L.FB[2], o2 ? g->Lb[i - 1] : nullptr,
+            (!o2 && keep) ? g->Lb[i - 1] : nullptr, sg, state(i), g->info, i == ns ? 1 : 0, g->cfg.gamma,
+            1.0 / h[0], 1.0 / h[1], 1.0 / h[2]);
+    }
+    return launch_check("Runge-Kutta step");
+}
+
 int enqueue_step(hog_grid* g, double dt_user)
 {
+    if (g->cfg.stepper != HOG_ADER) {
+        switch (g->P.nd * 10 + g->P.p) {
+        case 21: return enqueue_rk<2, 1>(g, dt_user);
+        case 22: return enqueue_rk<2, 2>(g, dt_user);
+        case 23: return enqueue_rk<2, 3>(g, dt_user);
+        case 31: return enqueue_rk<3, 1>(g, dt_user);
+        case 32: return enqueue_rk<3, 2>(g, dt_user);
+        case 33: return enqueue_rk<3, 3>(g, dt_user);
+        }
+        return fail(HOG_EINVAL, "unsupported dimension/order");
+    }
     if (g->P.p == 1) return g->P.nd == 3 ? enqueue_o2<3>(g, dt_user) : enqueue_o2<2>(g, dt_user);
     const int key = (g->cfg.precision == HOG_MIXED ? 100 : 0) + g->P.nd * 10 + g->P.p;
     switch (key) {
@@ -462,6 +583,10 @@ int hog_create(const hog_config* cfg, void* workspace, size_t bytes, void* hip_s
         g->F[d] = (d < P.nd && (P.p > 1 || cfg->debug)) ? reinterpret_cast<double*>(g->ws + P.off_F[d]) : nullptr;
     g->Q = cfg->debug ? static_cast<void*>(g->ws + P.off_Q) : nullptr;
     g->stage = reinterpret_cast<double*>(g->ws + P.off_stage);
+    for (int k = 0; k < 6; ++k) {
+        g->S[k] = (k >= 1 && k < P.nstages) ? reinterpret_cast<double*>(g->ws + P.off_S[k]) : nullptr;
+        g->Lb[k] = (k < P.nstages) ? reinterpret_cast<double*>(g->ws + P.off_L[k]) : nullptr;
+    }
     g->gate_on = g->gate_fixed = g->gate_net = false;
     g->gate = g->ws + P.off_gate;
     g->flags = reinterpret_cast<unsigned char*>(g->ws + P.off_flags);
@@ -770,6 +895,7 @@ int hog_set_gate(hog_grid* g, const float* params, double theta)
     g->gate_fixed = false;
     if (!params) { g->gate_on = g->gate_net = false; return HOG_OK; }
     if (g->P.p == 1) return fail(HOG_EINVAL, "the second-order scheme has no WENO weights to gate");
+    if (g->cfg.stepper != HOG_ADER) return fail(HOG_EINVAL, "the gate runs with the ADER step only");
     if (!(theta > 0.0 && theta < 1.0)) return fail(HOG_EINVAL, "theta must be in (0, 1)");
     const int rc = (g->P.nd == 3) ? set_gate_t<3>(g, params, theta) : set_gate_t<2>(g, params, theta);
     if (rc) { g->gate_on = g->gate_net = false; return rc; }
@@ -786,6 +912,7 @@ int hog_set_gate_flags(hog_grid* g, const unsigned char* flags)
         return HOG_OK;
     }
     if (g->P.p == 1) return fail(HOG_EINVAL, "the second-order scheme has no WENO weights to gate");
+    if (g->cfg.stepper != HOG_ADER) return fail(HOG_EINVAL, "the gate runs with the ADER step only");
     const long long N = box_size(g->P.I);
     for (long long i = 0; i < N; ++i)
         if (flags[i] > 1) return fail(HOG_EINVAL, "flags must be 0 or 1 (zone %lld)", i);

@@ -1195,12 +1195,13 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 // a5: Riemann solver at the face Gauss points and the space-time average of
 // the face flux (always summed in FP64).  One thread per face along axis dir.
 // ------------------------------------------------------------------------
-template <int D, typename T>
+// NPT points per face: 2^D for the ADER step (tangential axes and time),
+// 2^(D-1) for a Runge-Kutta stage (tangential axes only).
+template <int D, typename T, int NPT = (1 << D)>
 __global__ __launch_bounds__(256) void k_riemann(const T* __restrict__ FP, Box R, Box FB, int dir,
                                                  int solver, double gamma, double* __restrict__ F)
 {
     constexpr int NV = D + 2;
-    constexpr int NPT = 1 << D;
     const long long nF = box_size(FB), nR = box_size(R);
     const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nF) return;

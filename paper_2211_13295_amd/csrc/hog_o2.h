@@ -60,8 +60,9 @@ struct O2Args {
 // Modes of one zone: slopes S[d][v] and the time mode T[v] = dt dU/dt from the
 // mean u, the neighbours nb(d, v, side) along each axis (side 0 below, 1 above)
 // and lam[d] = dt/dx_d.  Returns false if a face value U +- S_d/2 or a face
-// state U +- S_d/2 + T/2 is inadmissible.
-template <int D, typename NB>
+// state U +- S_d/2 + T/2 is inadmissible.  Without HANCOCK (a Runge-Kutta
+// stage) the time mode is zero and only U +- S_d/2 is checked.
+template <int D, bool HANCOCK, typename NB>
 __device__ __forceinline__ bool o2_modes(const double* u, NB&& nb, const double* lam, double gm1,
                                          double (*S)[D + 2], double* T)
 {
@@ -78,6 +79,10 @@ __device__ __forceinline__ bool o2_modes(const double* u, NB&& nb, const double*
             Wm[v] = u[v] - 0.5 * S[d][v];
             Wp[v] = u[v] + 0.5 * S[d][v];
         }
+        if constexpr (!HANCOCK) {
+            ok = ok && admissible<D, double, true>(Wm, gm1) && admissible<D, double, true>(Wp, gm1);
+            continue;
+        }
         flux_dir<D, double, true>(Wm, gm1, d, Fm, pm, um);
         flux_dir<D, double, true>(Wp, gm1, d, Fp, pp, up);
         ok = ok && Wm[0] > 0.0 && pm > 0.0 && isfinite(Wm[0]) && isfinite(pm);
@@ -85,6 +90,7 @@ __device__ __forceinline__ bool o2_modes(const double* u, NB&& nb, const double*
 #pragma unroll
         for (int v = 0; v < NV; ++v) T[v] -= lam[d] * (Fp[v] - Fm[v]);
     }
+    if constexpr (!HANCOCK) return ok;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         double Wm[NV], Wp[NV];
@@ -107,9 +113,11 @@ struct O2Taps {
     Box FB[3];
 };
 
-template <int D, int SOLVER, bool TAPS>
+// RK: a Runge-Kutta stage -- no time mode, and instead of the new state the
+// kernel writes dt L of the interior zones to Lout ([v][zone], x fastest).
+template <int D, int SOLVER, bool TAPS, bool RK>
 __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ Uo, double* __restrict__ Un, Pad p,
-                                                 O2Args a, StepInfo* info, O2Taps tp)
+                                                 O2Args a, StepInfo* info, O2Taps tp, double* __restrict__ Lout)
 {
     using Sh = O2Shape<D>;
     constexpr int TX = Sh::TX, TY = Sh::TY, NT = TX * TY, NV = D + 2;
@@ -221,7 +229,7 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
                 const int off = (d == 0) ? 1 : LX;
                 return sU[v][side ? own_l + off : own_l - off];
             };
-            bool ok = o2_modes<D>(Uc, nb, lam, gm1, S, T);
+            bool ok = o2_modes<D, !RK>(Uc, nb, lam, gm1, S, T);
             if (!ok && a.positivity) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
@@ -266,17 +274,24 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
         for (int v = 0; v < NV; ++v) zp_prev[v] = Uc[v] + 0.5 * S[D - 1][v] + 0.5 * T[v];
         if (zface && m - 1 >= m0 && inner) {
             // update of the zone of plane m-1: increment of Fig. 6 added to the mean (Fig. 7)
-            double u[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) u[v] = Um[v] + (acc[v] - lam[D - 1] * Fzm[v]);
             const int i = ci, j = (D == 3) ? cj : m - 1, k = (D == 3) ? m - 1 : 0;
-            const long long pi = pad_index(p, i, j, k);
+            if constexpr (RK) {
+                const long long N = (long long)n0 * n1 * (D == 3 ? nm : 1);
+                const long long zi = ((long long)k * n1 + j) * n0 + i;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) Un[v * p.vs + pi] = u[v];
-            bool ok = true;
-            const double sp = signal_speed<D>(u, a.gamma, a.ih[0], a.ih[1], a.ih[2], ok);
-            if (ok) smax = fmax(smax, sp);
-            else atomicMin(&info->bad, (unsigned long long)(((long long)k * n1 + j) * n0 + i));
+                for (int v = 0; v < NV; ++v) Lout[v * N + zi] = acc[v] - lam[D - 1] * Fzm[v];
+            } else {
+                double u[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) u[v] = Um[v] + (acc[v] - lam[D - 1] * Fzm[v]);
+                const long long pi = pad_index(p, i, j, k);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Un[v * p.vs + pi] = u[v];
+                bool ok = true;
+                const double sp = signal_speed<D>(u, a.gamma, a.ih[0], a.ih[1], a.ih[2], ok);
+                if (ok) smax = fmax(smax, sp);
+                else atomicMin(&info->bad, (unsigned long long)(((long long)k * n1 + j) * n0 + i));
+            }
         }
         if (TAPS && zface && inner) {
             Box FB = (D == 3) ? FBz : FBy;
@@ -363,7 +378,7 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
         }
     }
     if (a.positivity && nfb) atomicAdd(&info->fallback, nfb);
-    cfl_reduce<D>(smax, true, 0, info);
+    if constexpr (!RK) cfl_reduce<D>(smax, true, 0, info);
 }
 
 } // namespace hog

@@ -22,6 +22,7 @@ TAP_MODES, TAP_STMODES, TAP_FLUX_X, TAP_FLUX_Y, TAP_FLUX_Z = 1, 2, 3, 4, 5
 RIEMANN = {"hllc": 0, "hll": 1, "rusanov": 2}
 BC = {"periodic": 0, "outflow": 1}
 PRECISION = {"fp64": 0, "mixed": 1}
+STEPPER = {"ader": 0, "rk2": 2, "rk3": 3, "rk4": 4}
 _ERRNAMES = {HOG_EINVAL: "EINVAL", HOG_ENOMEM: "ENOMEM", HOG_EDEVICE: "EDEVICE",
              HOG_ENONPHYS: "ENONPHYS", HOG_ESTATE: "ESTATE"}
 
@@ -37,7 +38,7 @@ class HogConfig(C.Structure):
         ("ndim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
         ("order", C.c_int), ("riemann", C.c_int), ("bc", C.c_int * 3),
         ("precision", C.c_int), ("linear_weno", C.c_int), ("debug", C.c_int),
-        ("positivity", C.c_int), ("reserved", C.c_int * 3),
+        ("positivity", C.c_int), ("stepper", C.c_int), ("reserved", C.c_int * 2),
         ("gamma", C.c_double), ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
         ("cfl", C.c_double), ("weno_eps", C.c_double), ("g3", C.c_double * 3), ("g4", C.c_double * 4),
     ]
@@ -105,7 +106,7 @@ def _check(rc):
 
 def make_config(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("periodic",) * 3,
                 linear_weno=False, debug=False, weno_eps=0.0, g3=(0, 0, 0), g4=(0, 0, 0, 0),
-                positivity=True, precision="fp64"):
+                positivity=True, precision="fp64", stepper="ader"):
     c = HogConfig()
     c.ndim = ndim
     c.nx, c.ny = int(n[0]), int(n[1])
@@ -118,6 +119,7 @@ def make_config(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("peri
     c.linear_weno = int(bool(linear_weno))
     c.debug = int(bool(debug))
     c.positivity = int(bool(positivity))
+    c.stepper = STEPPER[stepper] if isinstance(stepper, str) else int(stepper)
     c.gamma = gamma
     c.dx, c.dy = h[0], h[1]
     c.dz = h[2] if ndim == 3 else 1.0
