@@ -304,6 +304,65 @@ def second_order_line(hog, torch, args):
     return out
 
 
+def ader_vs_rk(hog, torch, args):
+    """Table IV on one MI355X: zone-updates/s of the ADER step and of the
+    Runge-Kutta scheme of the same order (2, 3, 5 stages; same reconstruction
+    and HLLC solver, face points in space only) on the 128^3 workload, FP64,
+    with per-stage times of each (ms per step, HIP events)."""
+    import icgen
+    n = args.n
+    pb = icgen.vortex3d_perturbed(n=n, seed=2)
+    rows = []
+    for order, stepper in ((2, "rk2"), (3, "rk3"), (4, "rk4")):
+        row = {"order": order}
+        # second-order steps take a fraction of a millisecond: time 10x as many so
+        # that the timed region is long against the GPU's clock ramp
+        steps = args.steps * (10 if order == 2 else 1)
+        for st in ("ader", stepper):
+            g = hog.Grid.from_problem(pb, order, stepper=st)
+            g.advance(steps // 2)
+            g.set_state(pb.U)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.advance(steps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            # stage breakdown from a separate run with the library's HIP events
+            g.set_state(pb.U)
+            g.profile(True)
+            g.advance(steps)
+            prof = g.profile_read()
+            g.profile(False)
+            g.close()
+            key = "ader" if st == "ader" else "rk"
+            row[key] = {"stepper": st, "steps": steps, "zone_updates_per_s": n ** 3 * steps / el,
+                        "ms_per_step": el * 1e3 / steps,
+                        "stage_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items() if v[1]}}
+        row["ader_over_rk"] = row["ader"]["zone_updates_per_s"] / row["rk"]["zone_updates_per_s"]
+        if order >= 3:
+            # dominant Runge-Kutta kernels at third/fourth order: the face-point
+            # evaluation (the "predictor" stage slot) and the reconstruction, both
+            # HBM-bound; roofline of the face-point kernel: per zone of the grown
+            # box it reads the spatial modes once and writes the face states once
+            from math import comb
+            ns, npt = comb(order - 1 + 3, 3), 2 * 3 * 4
+            zones_r = (n + 2) ** 3
+            alg = zones_r * (ns + npt) * 5 * 8
+            nst = {"rk2": 2, "rk3": 3, "rk4": 5}[stepper]
+            t = row["rk"]["stage_ms_per_step"]["predictor"] / nst / 1e3
+            row["rk"]["roofline"] = {"bound": "hbm", "kernel": f"k_face_points<3, {order - 1}>",
+                                     "achieved": alg / t / 1e9, "peak": 8000.0, "unit": "GB/s",
+                                     "frac": alg / t / 8e12, "traffic": None,
+                                     "alg_bytes_per_launch": alg, "avg_launch_ms": t * 1e3}
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    return {"metric": "zone-updates/s, ADER vs SSP Runge-Kutta of the same order (Table IV)", "unit": UNIT,
+            "n_gpus": 1, "steps": args.steps, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"3D vortex + density modes, {n}^3 periodic, HLLC, CFL 0.4, FP64; "
+                                   "second order: MC slopes (Hancock step for ADER), third/fourth: WENO"},
+            "rows": rows}
+
+
 def cpu_baseline(order, seconds):
     """The CPU oracle (plain FP64 C, OpenMP over zones) timed on this host on a
     bounded sample: whole steps of the same 3D workload at 32^3 (per-zone work
@@ -569,6 +628,9 @@ def main():
     ap.add_argument("--second-order", action="store_true",
                     help="instead of the benchmark line: the second-order scheme of Figs. 3-7 (HLL) on the "
                          "same workload; prints one JSON line")
+    ap.add_argument("--ader-vs-rk", action="store_true",
+                    help="instead of the benchmark line: ADER vs Runge-Kutta throughput at orders 2-4 (Table IV); "
+                         "prints one JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the predictor traffic record from two rocprofv3 counter files and exit")
     args = ap.parse_args()
@@ -602,6 +664,9 @@ def main():
         del x, y
     if args.second_order:
         print(json.dumps(second_order_line(hog, torch, args)), flush=True)
+        return
+    if args.ader_vs_rk:
+        print(json.dumps(ader_vs_rk(hog, torch, args)), flush=True)
         return
     if args.shock_workload:
         steps = 100 if args.shock_workload == "multiblast256" else 200

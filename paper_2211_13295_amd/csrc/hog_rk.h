@@ -21,7 +21,7 @@ template <int D, int P>
 __global__ __launch_bounds__(256) void k_face_points(const double* __restrict__ W, Box R, StepInfo* info,
                                                      double gamma, int positivity, double* __restrict__ FP)
 {
-    constexpr int NV = D + 2, NPT = 1 << (D - 1);
+    constexpr int NV = D + 2, NPT = 1 << (D - 1), NQ = 2 * D * NPT;
     constexpr Modes<D, P> M{};
     constexpr int NS = Modes<D, P>::NS;
     constexpr double g = 0.28867513459481288225;     // 2-point Gauss node on [-1/2, 1/2]
@@ -29,7 +29,12 @@ __global__ __launch_bounds__(256) void k_face_points(const double* __restrict__ 
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     bool fb = false;
     if (z < nR) {
-        // values at the face points, variable by variable (stored as they are made)
+        // values at the face points, variable by variable (stored as they are
+        // made); density and squared momentum of every point are kept for the
+        // admissibility check, which completes with the energy
+        double rho[NQ], ke[NQ];
+        bool ok = true;
+        const double gm1 = gamma - 1.0;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             double w[NS];
@@ -50,26 +55,25 @@ __global__ __launch_bounds__(256) void k_face_points(const double* __restrict__ 
 #pragma unroll
                         for (int m = 0; m < NS; ++m)
                             s += w[m] * (mleg(M.a[m], x[0]) * mleg(M.b[m], x[1]) * mleg(M.c[m], x[2]));
-                        FP[((long long)((d * 2 + side) * NPT + pt) * NV + v) * nR + z] = s;
+                        const int q = (d * 2 + side) * NPT + pt;
+                        FP[((long long)q * NV + v) * nR + z] = s;
+                        if (v == 0) { rho[q] = s; ke[q] = 0.0; }
+                        else if (v <= D) ke[q] += s * s;
+                        else {
+                            // the pressure as in admissible(): gm1 (E - 0.5 |m|^2 / rho)
+                            const double pr = gm1 * (s - 0.5 * ke[q] / rho[q]);
+                            ok = ok && rho[q] > 0.0 && pr > 0.0 && isfinite(rho[q]) && isfinite(pr);
+                        }
                     }
             }
         }
-        if (positivity) {
-            const double gm1 = gamma - 1.0;
+        if (positivity && !ok) {
+            fb = true;
 #pragma unroll
-            for (int q = 0; q < 2 * D * NPT; ++q) {
-                double u[NV];
+            for (int v = 0; v < NV; ++v) {
+                const double mean = W[(long long)v * nR + z];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) u[v] = FP[((long long)q * NV + v) * nR + z];
-                if (!admissible<D, double>(u, gm1)) fb = true;
-            }
-            if (fb) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const double mean = W[(long long)v * nR + z];
-#pragma unroll
-                    for (int q = 0; q < 2 * D * NPT; ++q) FP[((long long)q * NV + v) * nR + z] = mean;
-                }
+                for (int q = 0; q < NQ; ++q) FP[((long long)q * NV + v) * nR + z] = mean;
             }
         }
     }
