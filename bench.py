@@ -13,12 +13,15 @@ bracketed by device synchronisation.  Per-stage times come from HIP events
 recorded by the library on the stream its kernels run on.
 """
 import argparse
+import ctypes as C
 import hashlib
 import json
 import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -363,6 +366,54 @@ def ader_vs_rk(hog, torch, args):
             "rows": rows}
 
 
+def host_round_trip(hog, torch, args):
+    """The paper's per-step host round trip of the zone means (its U_skinny
+    array, Figs. 1-2, Table II) on one MI355X: each step copies the zone means
+    host -> device (pinned host buffer, zone-major [z][y][x][v] as U_skinny),
+    takes the step with the dt of the previous one, reads dt_next and copies the
+    new zone means back.  Against the resident loop (state stays in HBM)."""
+    import icgen
+    n = args.n
+    pb = icgen.vortex3d_perturbed(n=n, seed=2)
+    out = {"metric": "zone-updates/s with and without the per-step host round trip of the zone means",
+           "unit": UNIT, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"3D vortex + density modes, {n}^3 periodic, FP64, CFL 0.4"}, "rows": []}
+    for order, riemann in ((4, "hllc"), (2, "hll")):
+        steps = args.steps * (10 if order == 2 else 1)
+        g = hog.Grid.from_problem(pb, order, riemann=riemann)
+        host = torch.from_numpy(np.ascontiguousarray(np.moveaxis(pb.U, 0, -1))).pin_memory()
+        hp = C.c_void_p(host.data_ptr())
+        lib = hog.load()
+        dt = g.compute_dt()
+        for _ in range(3):                       # warm-up of the same loop
+            dt = g.step(dt)
+        g.set_state(pb.U)
+        dt = g.compute_dt()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            hog._check(lib.hog_set_state(g._h, hp, hog.AOS, hog.HOST))
+            dt = g.step(dt)
+            hog._check(lib.hog_get_state(g._h, hp, hog.AOS, hog.HOST))
+        torch.cuda.synchronize()
+        rt = time.perf_counter() - t0
+        g.set_state(pb.U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.advance(steps)
+        torch.cuda.synchronize()
+        res = time.perf_counter() - t0
+        g.close()
+        nbytes = n ** 3 * 5 * 8
+        out["rows"].append({"order": order, "riemann": riemann, "steps": steps,
+                            "resident_zone_updates_per_s": n ** 3 * steps / res, "resident_ms_per_step": res * 1e3 / steps,
+                            "round_trip_zone_updates_per_s": n ** 3 * steps / rt, "round_trip_ms_per_step": rt * 1e3 / steps,
+                            "bytes_each_way_per_step": nbytes,
+                            "transfer_ms_per_step": (rt - res) * 1e3 / steps})
+        print(json.dumps(out["rows"][-1]), file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(order, seconds):
     """The CPU oracle (plain FP64 C, OpenMP over zones) timed on this host on a
     bounded sample: whole steps of the same 3D workload at 32^3 (per-zone work
@@ -628,6 +679,9 @@ def main():
     ap.add_argument("--second-order", action="store_true",
                     help="instead of the benchmark line: the second-order scheme of Figs. 3-7 (HLL) on the "
                          "same workload; prints one JSON line")
+    ap.add_argument("--host-round-trip", action="store_true",
+                    help="instead of the benchmark line: steps with the paper's per-step host round trip of the "
+                         "zone means vs the resident loop; prints one JSON line")
     ap.add_argument("--ader-vs-rk", action="store_true",
                     help="instead of the benchmark line: ADER vs Runge-Kutta throughput at orders 2-4 (Table IV); "
                          "prints one JSON line")
@@ -667,6 +721,9 @@ def main():
         return
     if args.ader_vs_rk:
         print(json.dumps(ader_vs_rk(hog, torch, args)), flush=True)
+        return
+    if args.host_round_trip:
+        print(json.dumps(host_round_trip(hog, torch, args)), flush=True)
         return
     if args.shock_workload:
         steps = 100 if args.shock_workload == "multiblast256" else 200
