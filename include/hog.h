@@ -57,7 +57,11 @@ enum {
     HOG_ESTATE = -5      /* call out of order (e.g. step before set_state) */
 };
 
-enum { HOG_PERIODIC = 0, HOG_OUTFLOW = 1 };            /* per-axis boundary */
+/* Per-axis boundary.  HOG_EXTERNAL (last active axis only: z in 3D, y in 2D,
+ * ADER stepping only): the caller supplies the three ghost layers below and
+ * above the interior along that axis with hog_set_state_ext, e.g. from the
+ * neighbouring slabs of a larger mesh (see hog_stream_*). */
+enum { HOG_PERIODIC = 0, HOG_OUTFLOW = 1, HOG_EXTERNAL = 2 };
 enum { HOG_HLLC = 0, HOG_HLL = 1, HOG_RUSANOV = 2 };   /* Riemann solver */
 /* Arithmetic of the path.  HOG_FP64: everything in FP64.  HOG_MIXED: the
  * reconstruction coefficients, predictor, face states and Riemann solver in
@@ -96,7 +100,7 @@ typedef struct hog_config {
     int order;           /* 2, 3 or 4 (polynomial degree p = order - 1); 2 is the
                             scheme of Figs. 3-7 and needs precision HOG_FP64 */
     int riemann;         /* HOG_HLLC | HOG_HLL | HOG_RUSANOV */
-    int bc[3];           /* per axis HOG_PERIODIC | HOG_OUTFLOW */
+    int bc[3];           /* per axis HOG_PERIODIC | HOG_OUTFLOW | HOG_EXTERNAL (last axis) */
     int precision;       /* HOG_FP64 | HOG_MIXED */
     int linear_weno;     /* 1: WENO nonlinear weights replaced by the linear ones */
     int debug;           /* 1: keep the space-time modes for HOG_TAP_STMODES */
@@ -150,6 +154,14 @@ int hog_set_state(hog_grid* g, const double* U, int layout, int where);
  * call synchronises the stream.  Errors: HOG_EINVAL, HOG_ESTATE, HOG_EDEVICE. */
 int hog_get_state(hog_grid* g, double* U, int layout, int where);
 
+/* Like hog_set_state (SoA only) for a grid whose last axis is HOG_EXTERNAL:
+ * U holds the interior and the three ghost layers below and above along that
+ * axis, [nv][nz+6][ny][nx] in 3D or [nv][ny+6][nx] in 2D (layer 0 is the
+ * lowest ghost layer).  The ghost layers are used as given by the next step;
+ * the other axes' ghosts are filled from their boundary types as usual.
+ * Errors: HOG_EINVAL (NULL, or the last axis not external), HOG_EDEVICE. */
+int hog_set_state_ext(hog_grid* g, const double* U, int where);
+
 /* CFL time step of the current state, dt = cfl / max_zones sum_d
  * (|u_d| + c) / dx_d (paper Fig. 7, Eval_Tstep_Ptwise with a min reduction).
  * Synchronises.  Errors: HOG_ENONPHYS (see hog_last_bad_zone), HOG_ESTATE. */
@@ -196,6 +208,49 @@ int hog_profile_read(hog_grid* g, double* ms, int* launches, int nstages);
  * that used the positivity fallback in the last step.  Pointers may be NULL.
  * Errors: HOG_EINVAL, HOG_EDEVICE. */
 int hog_stats(hog_grid* g, double* t, double* dt, long long* fallback_zones);
+
+/* ---------------------------------------------------------------------
+ * Slab streaming of a host-resident mesh (Sec. II.2 and Sec. V: each patch of
+ * a mesh larger than the GPU's memory is moved to the GPU every step).  The
+ * mesh, of any size along its last axis, lives in two pinned host buffers;
+ * every step moves it through the GPU in slabs of at most slab_planes planes
+ * of the last axis, each with the three ghost layers of its neighbours, on two
+ * slab grids: the copies of one slab (in on the copy stream, out after its
+ * step) overlap the step of the other.  The result equals the in-core
+ * hog_step zone for zone (the fallback count differs: it counts each slab's
+ * grown box).  ADER stepping only: a Runge-Kutta stage would need an
+ * exchange of its own.
+ * --------------------------------------------------------------------- */
+typedef struct hog_stream hog_stream;
+
+/* Device bytes for a mesh (its own last-axis boundary periodic or outflow,
+ * stepper HOG_ADER, debug 0) streamed in slabs of slab_planes planes
+ * (1 <= slab_planes <= the last axis).  Errors: HOG_EINVAL. */
+int hog_stream_workspace_size(const hog_config* mesh, int slab_planes, size_t* bytes);
+
+/* Bind a device workspace (256-byte aligned, hog_stream_workspace_size bytes,
+ * borrowed), two host buffers of nv*nx*ny*nz doubles each (SoA [v][nz][ny][nx];
+ * pinned host memory, e.g. hipHostMalloc or a pinned torch tensor; borrowed;
+ * host_a holds the initial state, host_b receives the next one and the two
+ * alternate) and two different HIP streams (compute and copy).
+ * Errors: HOG_EINVAL, HOG_ENOMEM (workspace too small), HOG_EDEVICE. */
+int hog_stream_create(const hog_config* mesh, int slab_planes, void* workspace, size_t bytes, double* host_a,
+                      double* host_b, void* compute_stream, void* copy_stream, hog_stream** out);
+int hog_stream_destroy(hog_stream* s);
+
+/* CFL dt of the current state (one pass of the slabs); synchronises.
+ * Errors: HOG_ENONPHYS, HOG_EDEVICE. */
+int hog_stream_compute_dt(hog_stream* s, double* dt);
+
+/* One step of the whole mesh with dt (dt = 0: the CFL dt of the current
+ * state, from the previous step or one extra pass); the new state goes to the
+ * other host buffer, which becomes current.  Synchronises; dt_next (may be
+ * NULL) receives the CFL dt of the new state.  On HOG_ENONPHYS the current
+ * state is kept.  Errors: HOG_EINVAL, HOG_ENONPHYS, HOG_EDEVICE. */
+int hog_stream_step(hog_stream* s, double dt, double* dt_next);
+
+/* The host buffer that holds the current state. */
+int hog_stream_state(hog_stream* s, double** host_state);
 
 /* ---------------------------------------------------------------------
  * Learned smooth-zone gate (not in the paper; a cheaper reconstruction in

@@ -48,6 +48,7 @@ struct Plan {
     int n[3];
     Pad pad;
     Box I, AX, BY, R, FB[3];
+    Box E;           // interior extended by the ghost layers of an external last axis (else I)
     int ms, mst;
     // byte offsets in the workspace
     size_t off_info, off_U[2], off_A, off_B, off_W, off_FP, off_F[3], off_Q, off_stage;
@@ -70,7 +71,14 @@ int check_cfg(const hog_config* c)
     if (c->ndim == 2 && c->nz != 1) return fail(HOG_EINVAL, "nz must be 1 in 2D");
     if (c->riemann < 0 || c->riemann > 2) return fail(HOG_EINVAL, "unknown Riemann solver %d", c->riemann);
     for (int d = 0; d < 3; ++d)
-        if (c->bc[d] != HOG_PERIODIC && c->bc[d] != HOG_OUTFLOW) return fail(HOG_EINVAL, "bad boundary type on axis %d", d);
+        if (c->bc[d] != HOG_PERIODIC && c->bc[d] != HOG_OUTFLOW && c->bc[d] != HOG_EXTERNAL)
+            return fail(HOG_EINVAL, "bad boundary type on axis %d", d);
+    for (int d = 0; d < 3; ++d)
+        if (c->bc[d] == HOG_EXTERNAL && d != c->ndim - 1)
+            return fail(HOG_EINVAL, "an external boundary is supported on the last axis only (axis %d)", d);
+    if (c->bc[c->ndim - 1] == HOG_EXTERNAL && c->stepper != HOG_ADER)
+        return fail(HOG_EINVAL, "an external boundary needs the one-exchange ADER step (Runge-Kutta stages would "
+                                "need new ghost layers each)");
     if (c->precision != HOG_FP64 && c->precision != HOG_MIXED)
         return fail(HOG_EINVAL, "precision %d not supported", c->precision);
     if (c->precision == HOG_MIXED && c->debug)
@@ -118,6 +126,11 @@ void plan(const hog_config* c, Plan* P)
     P->pad.vs = (long long)P->pad.np[0] * P->pad.np[1] * P->pad.np[2];
     const int nx = P->n[0], ny = P->n[1], nz = P->n[2];
     P->I = make_box(0, 0, 0, nx, ny, nz);
+    P->E = P->I;
+    if (c->bc[nd - 1] == HOG_EXTERNAL) {
+        if (nd == 3) P->E = make_box(0, 0, -kGhostZones, nx, ny, nz + 2 * kGhostZones);
+        else P->E = make_box(0, -kGhostZones, 0, nx, ny + 2 * kGhostZones, 1);
+    }
     if (nd == 3) {
         P->AX = make_box(-1, -3, -3, nx + 2, ny + 6, nz + 6);
         P->BY = make_box(-1, -1, -3, nx + 2, ny + 2, nz + 6);
@@ -150,7 +163,7 @@ void plan(const hog_config* c, Plan* P)
     for (int d = 0; d < 3; ++d)
         P->off_F[d] = (d < nd && (!o2 || c->debug)) ? take(sizeof(double) * nv * box_size(P->FB[d])) : 0;
     P->off_Q = c->debug ? take(sizeof(double) * P->mst * nv * box_size(P->R)) : 0;
-    P->off_stage = take(sizeof(double) * nv * box_size(P->I));
+    P->off_stage = take(sizeof(double) * nv * box_size(P->E));
     P->nstages = rk_nstages(c->stepper);
     for (int k = 0; k < 6; ++k) { P->off_S[k] = 0; P->off_L[k] = 0; }
     for (int k = 1; k < P->nstages; ++k) P->off_S[k] = take(sizeof(double) * nv * P->pad.vs);
@@ -661,6 +674,31 @@ int hog_set_state(hog_grid* g, const double* U, int layout, int where)
     return HOG_OK;
 }
 
+int hog_set_state_ext(hog_grid* g, const double* U, int where)
+{
+    if (!g || !U) return fail(HOG_EINVAL, "NULL argument");
+    if (where != HOG_HOST && where != HOG_DEVICE) return fail(HOG_EINVAL, "unknown location %d", where);
+    const Plan& L = g->P;
+    if (g->cfg.bc[L.nd - 1] != HOG_EXTERNAL) return fail(HOG_EINVAL, "the last axis is not external");
+    const long long NE = box_size(L.E);
+    const double* src = U;
+    if (where == HOG_HOST) {
+        HIP_TRY(hipMemcpyAsync(g->stage, U, sizeof(double) * L.nv * NE, hipMemcpyHostToDevice, g->stream));
+        HIP_TRY(hipStreamSynchronize(g->stream));
+        src = g->stage;
+    }
+    if (L.nd == 3) k_pack<3><<<nblocks(NE, 256), 256, 0, g->stream>>>(src, g->U[g->cur], L.pad, L.E, 0);
+    else k_pack<2><<<nblocks(NE, 256), 256, 0, g->stream>>>(src, g->U[g->cur], L.pad, L.E, 0);
+    int rc = launch_check("pack");
+    if (rc) return rc;
+    rc = enqueue_cfl(g, g->cur);
+    if (rc) return rc;
+    g->have_state = true;
+    g->smax_valid = true;
+    g->have_step = false;
+    return HOG_OK;
+}
+
 int hog_get_state(hog_grid* g, double* U, int layout, int where)
 {
     if (!g || !U) return fail(HOG_EINVAL, "NULL argument");
@@ -1138,6 +1176,324 @@ int hog_mlp_predict(hog_mlp* m, const float* X, int n, float* logits)
                                                                       nullptr, nullptr, logits + s0);
     }
     return launch_check("mlp predict");
+}
+
+} // extern "C"
+
+// ------------------------------------------------------------------------
+// Slab streaming of a host-resident mesh.  The paper keeps each patch of a
+// large mesh in host memory and moves it to the GPU every time step (Sec.
+// II.2 and Sec. V, Tables I-II); here a mesh of any size along its last axis
+// lives in two pinned host buffers (current and next state) and is stepped
+// slab by slab through two patch grids on the device: while one slab is
+// computed on the compute stream, the next one is copied in and the previous
+// one copied out on the copy stream.  Each slab carries the three ghost
+// layers of its neighbours (an HOG_EXTERNAL last axis), so the result equals
+// the in-core step zone for zone.  One exchange per step is what the ADER
+// step needs; Runge-Kutta stages would need one each, so they are rejected.
+// ------------------------------------------------------------------------
+namespace {
+
+// fold one slab's step info into the accumulator: max signal speed, first bad
+// zone (in mesh numbering), fallback count
+__global__ void k_fold_info(const StepInfo* __restrict__ src, StepInfo* acc, long long zone_offset, int reset)
+{
+    if (reset) { acc->smax_bits = 0ull; acc->bad = ULLONG_MAX; acc->fallback = 0ull; }
+    if (src->smax_bits > acc->smax_bits) acc->smax_bits = src->smax_bits;
+    if (src->bad != ULLONG_MAX) {
+        const unsigned long long b = src->bad + (unsigned long long)zone_offset;
+        if (b < acc->bad) acc->bad = b;
+    }
+    acc->fallback += src->fallback;
+}
+
+} // namespace
+
+struct hog_stream {
+    hog_config mesh;
+    int nd, nv, nlast, pn, npatch;
+    long long plane, nmesh;        // zones per plane of the last axis; zones of the mesh
+    double* host[2];               // pinned, caller-owned: current / next state, SoA [v][nlast][plane]
+    int cur;
+    hipStream_t cs, xs;
+    hog_grid* g[3];                // slab grids: two of pn planes, one for a shorter last slab
+    double* in[2];                 // device staging, [v][pn + 6][plane]
+    double* out[2];                // device staging, [v][pn][plane]
+    StepInfo* acc;                 // folded step info of the whole mesh
+    hipEvent_t h2d[2], comp[2], done[2];
+    double smax;                   // max signal speed of the current state (< 0: unknown)
+    long long last_bad;
+};
+
+namespace {
+
+struct StreamPlan {
+    hog_config pcfg, tcfg;   // slab configs (full and last)
+    int npatch, tail;        // planes of the last slab if shorter, else 0
+    size_t off_g[3], bytes_g[3], off_in[2], off_out[2], off_acc, total;
+};
+
+int stream_plan(const hog_config* m, int pn, StreamPlan* S)
+{
+    int rc = check_cfg(m);
+    if (rc) return rc;
+    const int nd = m->ndim;
+    const int nlast = (nd == 3) ? m->nz : m->ny;
+    if (m->bc[nd - 1] == HOG_EXTERNAL) return fail(HOG_EINVAL, "the mesh's own last-axis boundary must be periodic or outflow");
+    if (m->stepper != HOG_ADER) return fail(HOG_EINVAL, "streaming needs the one-exchange ADER step");
+    if (m->debug) return fail(HOG_EINVAL, "no debug taps when streaming");
+    if (pn < 1 || pn > nlast) return fail(HOG_EINVAL, "slab planes must be in [1, %d]", nlast);
+    S->npatch = (nlast + pn - 1) / pn;
+    S->tail = (nlast % pn) ? nlast % pn : 0;
+    S->pcfg = *m;
+    S->pcfg.bc[nd - 1] = HOG_EXTERNAL;
+    if (nd == 3) S->pcfg.nz = pn; else S->pcfg.ny = pn;
+    S->tcfg = S->pcfg;
+    if (S->tail) { if (nd == 3) S->tcfg.nz = S->tail; else S->tcfg.ny = S->tail; }
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    for (int k = 0; k < 3; ++k) {
+        S->bytes_g[k] = 0;
+        S->off_g[k] = 0;
+        if (k == 2 && !S->tail) continue;
+        rc = hog_workspace_size(k == 2 ? &S->tcfg : &S->pcfg, &S->bytes_g[k]);
+        if (rc) return rc;
+        S->off_g[k] = take(S->bytes_g[k]);
+    }
+    const long long plane = (long long)m->nx * (nd == 3 ? m->ny : 1);
+    const int nv = nd + 2;
+    for (int k = 0; k < 2; ++k) {
+        S->off_in[k] = take(sizeof(double) * nv * (pn + 2 * kGhostZones) * plane);
+        S->off_out[k] = take(sizeof(double) * nv * pn * plane);
+    }
+    S->off_acc = take(sizeof(StepInfo));
+    S->total = o;
+    return HOG_OK;
+}
+
+// mesh plane that supplies plane z of the padded last axis (ghosts by the mesh's boundary type)
+int mesh_plane(int z, int n, int bc)
+{
+    if (z >= 0 && z < n) return z;
+    if (bc == HOG_PERIODIC) return ((z % n) + n) % n;
+    return z < 0 ? 0 : n - 1;
+}
+
+// enqueue the copy of slab p (planes [z0 - 3, z0 + np + 3) of the current host state) into in[slot],
+// laid out [v][np + 6][plane] as the slab grid's extended box wants it
+int stream_h2d(hog_stream* s, int p, int slot)
+{
+    const int z0 = p * s->pn, np = std::min(s->pn, s->nlast - z0), G = kGhostZones;
+    const int bc = s->mesh.bc[s->nd - 1];
+    const size_t pb = sizeof(double) * s->plane;
+    int z = -G;
+    while (z < np + G) {
+        // longest run of consecutive mesh planes starting at z
+        const int m0 = mesh_plane(z0 + z, s->nlast, bc);
+        int len = 1;
+        while (z + len < np + G && mesh_plane(z0 + z + len, s->nlast, bc) == m0 + len) ++len;
+        for (int v = 0; v < s->nv; ++v)
+            HIP_TRY(hipMemcpyAsync(s->in[slot] + ((long long)v * (np + 2 * G) + (z + G)) * s->plane,
+                                   s->host[s->cur] + ((long long)v * s->nlast + m0) * s->plane, pb * len,
+                                   hipMemcpyHostToDevice, s->xs));
+        z += len;
+    }
+    return HOG_OK;
+}
+
+// staged slab -> the slab grid's padded state, ghost layers of the external axis included
+int stream_pack(hog_stream* s, hog_grid* g, int slot)
+{
+    const Plan& L = g->P;
+    const long long NE = box_size(L.E);
+    const double* src = s->in[slot];
+    if (L.nd == 3) k_pack<3><<<nblocks(NE, 256), 256, 0, s->cs>>>(src, g->U[g->cur], L.pad, L.E, 0);
+    else k_pack<2><<<nblocks(NE, 256), 256, 0, s->cs>>>(src, g->U[g->cur], L.pad, L.E, 0);
+    return launch_check("slab pack");
+}
+
+} // namespace
+
+extern "C" {
+
+int hog_stream_workspace_size(const hog_config* mesh, int slab_planes, size_t* bytes)
+{
+    if (!bytes) return fail(HOG_EINVAL, "bytes is NULL");
+    StreamPlan S;
+    int rc = stream_plan(mesh, slab_planes, &S);
+    if (rc) return rc;
+    *bytes = S.total;
+    return HOG_OK;
+}
+
+int hog_stream_create(const hog_config* mesh, int slab_planes, void* workspace, size_t bytes, double* host_a,
+                      double* host_b, void* compute_stream, void* copy_stream, hog_stream** out)
+{
+    g_err[0] = 0;
+    if (!out || !host_a || !host_b || !workspace) return fail(HOG_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (compute_stream == copy_stream) return fail(HOG_EINVAL, "the compute and copy streams must differ");
+    StreamPlan S;
+    int rc = stream_plan(mesh, slab_planes, &S);
+    if (rc) return rc;
+    if (bytes < S.total) return fail(HOG_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, S.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(HOG_EINVAL, "workspace must be 256-byte aligned");
+    hog_stream* s = new (std::nothrow) hog_stream();
+    if (!s) return fail(HOG_ENOMEM, "host allocation failed");
+    char* ws = static_cast<char*>(workspace);
+    s->mesh = *mesh;
+    s->nd = mesh->ndim;
+    s->nv = s->nd + 2;
+    s->nlast = (s->nd == 3) ? mesh->nz : mesh->ny;
+    s->pn = slab_planes;
+    s->npatch = S.npatch;
+    s->plane = (long long)mesh->nx * (s->nd == 3 ? mesh->ny : 1);
+    s->nmesh = s->plane * s->nlast;
+    s->host[0] = host_a;
+    s->host[1] = host_b;
+    s->cur = 0;
+    s->cs = static_cast<hipStream_t>(compute_stream);
+    s->xs = static_cast<hipStream_t>(copy_stream);
+    s->smax = -1.0;
+    s->last_bad = -1;
+    for (int k = 0; k < 3; ++k) s->g[k] = nullptr;
+    for (int k = 0; k < 2; ++k) s->h2d[k] = s->comp[k] = s->done[k] = nullptr;
+    auto cleanup = [&](int code) {
+        for (int k = 0; k < 3; ++k) hog_destroy(s->g[k]);
+        for (int k = 0; k < 2; ++k) {
+            if (s->h2d[k]) (void)hipEventDestroy(s->h2d[k]);
+            if (s->comp[k]) (void)hipEventDestroy(s->comp[k]);
+            if (s->done[k]) (void)hipEventDestroy(s->done[k]);
+        }
+        delete s;
+        return code;
+    };
+    for (int k = 0; k < 3; ++k) {
+        if (!S.bytes_g[k]) continue;
+        rc = hog_create(k == 2 ? &S.tcfg : &S.pcfg, ws + S.off_g[k], S.bytes_g[k], compute_stream, &s->g[k]);
+        if (rc) return cleanup(rc);
+    }
+    for (int k = 0; k < 2; ++k) {
+        s->in[k] = reinterpret_cast<double*>(ws + S.off_in[k]);
+        s->out[k] = reinterpret_cast<double*>(ws + S.off_out[k]);
+        if (hipEventCreateWithFlags(&s->h2d[k], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&s->comp[k], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&s->done[k], hipEventDisableTiming) != hipSuccess)
+            return cleanup(fail(HOG_EDEVICE, "event creation failed"));
+        if (hipEventRecord(s->done[k], s->xs) != hipSuccess) return cleanup(fail(HOG_EDEVICE, "event record failed"));
+    }
+    s->acc = reinterpret_cast<StepInfo*>(ws + S.off_acc);
+    *out = s;
+    return HOG_OK;
+}
+
+int hog_stream_destroy(hog_stream* s)
+{
+    if (!s) return HOG_OK;
+    (void)hipStreamSynchronize(s->cs);
+    (void)hipStreamSynchronize(s->xs);
+    for (int k = 0; k < 3; ++k) hog_destroy(s->g[k]);
+    for (int k = 0; k < 2; ++k) {
+        (void)hipEventDestroy(s->h2d[k]);
+        (void)hipEventDestroy(s->comp[k]);
+        (void)hipEventDestroy(s->done[k]);
+    }
+    delete s;
+    return HOG_OK;
+}
+
+int hog_stream_state(hog_stream* s, double** host_state)
+{
+    if (!s || !host_state) return fail(HOG_EINVAL, "NULL argument");
+    *host_state = s->host[s->cur];
+    return HOG_OK;
+}
+
+// One pass over the slabs: with step = 0 the CFL reduction of the current
+// state, else one step of every slab with dt, new state into the other buffer.
+static int stream_pass(hog_stream* s, double dt, int step)
+{
+    for (int p = 0; p < s->npatch; ++p) {
+        const int slot = p & 1;
+        const int z0 = p * s->pn, np = std::min(s->pn, s->nlast - z0);
+        hog_grid* g = (np == s->pn) ? s->g[slot] : s->g[2];
+        HIP_TRY(hipStreamWaitEvent(s->xs, s->done[slot], 0));
+        int rc = stream_h2d(s, p, slot);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(s->h2d[slot], s->xs));
+        HIP_TRY(hipStreamWaitEvent(s->cs, s->h2d[slot], 0));
+        rc = stream_pack(s, g, slot);
+        if (rc) return rc;
+        const Plan& L = g->P;
+        if (step) {
+            rc = enqueue_step(g, dt);
+            if (rc) return rc;
+            g->cur ^= 1;
+            const long long N = box_size(L.I);
+            if (L.nd == 3) k_unpack<3><<<nblocks(N, 256), 256, 0, s->cs>>>(g->U[g->cur], s->out[slot], L.pad, L.I, 0);
+            else k_unpack<2><<<nblocks(N, 256), 256, 0, s->cs>>>(g->U[g->cur], s->out[slot], L.pad, L.I, 0);
+        } else {
+            rc = enqueue_cfl(g, g->cur);
+            if (rc) return rc;
+        }
+        k_fold_info<<<1, 1, 0, s->cs>>>(g->info, s->acc, (long long)z0 * s->plane, p == 0 ? 1 : 0);
+        rc = launch_check("slab step");
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(s->comp[slot], s->cs));
+        HIP_TRY(hipStreamWaitEvent(s->xs, s->comp[slot], 0));
+        if (step) {
+            const size_t bytes = sizeof(double) * (size_t)np * s->plane;
+            for (int v = 0; v < s->nv; ++v)
+                HIP_TRY(hipMemcpyAsync(s->host[s->cur ^ 1] + ((long long)v * s->nlast + z0) * s->plane,
+                                       s->out[slot] + (long long)v * np * s->plane, bytes, hipMemcpyDeviceToHost, s->xs));
+        }
+        HIP_TRY(hipEventRecord(s->done[slot], s->xs));
+    }
+    HIP_TRY(hipStreamSynchronize(s->cs));
+    HIP_TRY(hipStreamSynchronize(s->xs));
+    return HOG_OK;
+}
+
+int hog_stream_compute_dt(hog_stream* s, double* dt)
+{
+    if (!s || !dt) return fail(HOG_EINVAL, "NULL argument");
+    int rc = stream_pass(s, 0.0, 0);
+    if (rc) return rc;
+    StepInfo si;
+    HIP_TRY(hipMemcpy(&si, s->acc, sizeof si, hipMemcpyDeviceToHost));
+    if (si.bad != ULLONG_MAX) {
+        s->last_bad = (long long)si.bad;
+        return fail(HOG_ENONPHYS, "non-physical state in zone %lld", s->last_bad);
+    }
+    s->smax = smax_of(si);
+    *dt = s->mesh.cfl / s->smax;
+    return HOG_OK;
+}
+
+int hog_stream_step(hog_stream* s, double dt, double* dt_next)
+{
+    if (!s) return fail(HOG_EINVAL, "NULL handle");
+    if (!(dt > 0.0) || !std::isfinite(dt)) {
+        if (dt != 0.0) return fail(HOG_EINVAL, "dt must be finite and > 0, or 0 for the CFL dt (got %g)", dt);
+        if (!(s->smax > 0.0)) {
+            double d;
+            int rc = hog_stream_compute_dt(s, &d);
+            if (rc) return rc;
+        }
+        dt = s->mesh.cfl / s->smax;
+    }
+    int rc = stream_pass(s, dt, 1);
+    if (rc) return rc;
+    StepInfo si;
+    HIP_TRY(hipMemcpy(&si, s->acc, sizeof si, hipMemcpyDeviceToHost));
+    if (si.bad != ULLONG_MAX) {
+        s->last_bad = (long long)si.bad;
+        return fail(HOG_ENONPHYS, "step produced a non-physical state in zone %lld", s->last_bad);
+    }
+    s->cur ^= 1;
+    s->smax = smax_of(si);
+    if (dt_next) *dt_next = s->mesh.cfl / s->smax;
+    return HOG_OK;
 }
 
 } // extern "C"

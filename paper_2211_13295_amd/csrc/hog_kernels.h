@@ -104,9 +104,15 @@ __global__ __launch_bounds__(256) void k_ghost(double* __restrict__ U, Pad p, in
     long long r = idx / p.np[0];
     int j = (int)(r % p.np[1]) - p.off[1];
     int k = (int)(r / p.np[1]) - p.off[2];
-    const bool inside = i >= 0 && i < n0 && j >= 0 && j < n1 && k >= 0 && k < n2;
-    if (inside) return;
+    // an external last axis (bc 2) keeps the ghost layers the caller supplied:
+    // zones outside only along it are left alone, the others are filled along
+    // the first axes from the supplied layer
+    const bool ext = (D == 3 ? bc2 : bc1) == 2;
+    const bool in01 = i >= 0 && i < n0 && (D == 3 ? (j >= 0 && j < n1) : true);
+    const bool inlast = (D == 3) ? (k >= 0 && k < n2) : (j >= 0 && j < n1);
+    if (in01 && (inlast || ext)) return;
     auto src = [](int x, int n, int bc) {
+        if (bc == 2) return x;
         if (bc == 0) { x %= n; return x < 0 ? x + n : x; }
         return x < 0 ? 0 : (x >= n ? n - 1 : x);
     };

@@ -40,10 +40,12 @@ __device__ __forceinline__ double mc_slope(double a, double b, double cfac)
 
 // Zone index along one axis after the boundary condition: clamp to the two
 // zones beyond the interior that the scheme reads, then wrap (periodic) or
-// clamp (outflow).  Periodic axes have n >= 3, so one wrap suffices.
+// clamp (outflow); an external axis reads the caller's ghost layers.
+// Periodic axes have n >= 3, so one wrap suffices.
 __device__ __forceinline__ int o2_src(int x, int n, int bc)
 {
     x = min(max(x, -2), n + 1);
+    if (bc == 2) return x;
     if (bc == 0) return x < 0 ? x + n : (x >= n ? x - n : x);
     return min(max(x, 0), n - 1);
 }

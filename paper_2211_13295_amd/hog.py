@@ -20,7 +20,7 @@ SOA, AOS = 0, 1
 HOST, DEVICE = 0, 1
 TAP_MODES, TAP_STMODES, TAP_FLUX_X, TAP_FLUX_Y, TAP_FLUX_Z = 1, 2, 3, 4, 5
 RIEMANN = {"hllc": 0, "hll": 1, "rusanov": 2}
-BC = {"periodic": 0, "outflow": 1}
+BC = {"periodic": 0, "outflow": 1, "external": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 STEPPER = {"ader": 0, "rk2": 2, "rk3": 3, "rk4": 4}
 _ERRNAMES = {HOG_EINVAL: "EINVAL", HOG_ENOMEM: "ENOMEM", HOG_EDEVICE: "EDEVICE",
@@ -63,6 +63,13 @@ def load():
     L.hog_destroy.argtypes = [vp]
     L.hog_set_state.argtypes = [vp, vp, C.c_int, C.c_int]
     L.hog_get_state.argtypes = [vp, vp, C.c_int, C.c_int]
+    L.hog_set_state_ext.argtypes = [vp, vp, C.c_int]
+    L.hog_stream_workspace_size.argtypes = [cp, C.c_int, C.POINTER(C.c_size_t)]
+    L.hog_stream_create.argtypes = [cp, C.c_int, vp, C.c_size_t, vp, vp, vp, vp, C.POINTER(vp)]
+    L.hog_stream_destroy.argtypes = [vp]
+    L.hog_stream_compute_dt.argtypes = [vp, C.POINTER(C.c_double)]
+    L.hog_stream_step.argtypes = [vp, C.c_double, C.POINTER(C.c_double)]
+    L.hog_stream_state.argtypes = [vp, C.POINTER(vp)]
     L.hog_compute_dt.argtypes = [vp, C.POINTER(C.c_double)]
     L.hog_step.argtypes = [vp, C.c_double, vp]
     L.hog_advance.argtypes = [vp, C.c_int, C.c_double, C.POINTER(C.c_double)]
@@ -91,6 +98,9 @@ def load():
         getattr(L, f).restype = C.c_int
     L.hog_last_bad_zone.argtypes = [vp]
     L.hog_last_bad_zone.restype = C.c_longlong
+    for f in ("hog_set_state_ext", "hog_stream_workspace_size", "hog_stream_create", "hog_stream_destroy",
+              "hog_stream_compute_dt", "hog_stream_step", "hog_stream_state"):
+        getattr(L, f).restype = C.c_int
     for f in ("hog_workspace_size", "hog_create", "hog_destroy", "hog_set_state", "hog_get_state",
               "hog_compute_dt", "hog_step", "hog_advance", "hog_debug_tap", "hog_profile_enable",
               "hog_profile_read", "hog_stats"):
@@ -195,6 +205,12 @@ class Grid:
         assert a.size == self.nv * self.nzones
         _check(load().hog_set_state(self._h, a.ctypes.data_as(C.c_void_p), layout, HOST))
 
+    def set_state_ext(self, U):
+        """Interior plus the three ghost layers below and above along an
+        external last axis: SoA [v][n_last + 6][...] (host array)."""
+        a = np.ascontiguousarray(U, dtype=np.float64)
+        _check(load().hog_set_state_ext(self._h, a.ctypes.data_as(C.c_void_p), HOST))
+
     def get_state(self, layout=SOA):
         shape = self.shape if layout == SOA else self.shape[1:] + (self.nv,)
         out = np.empty(shape, dtype=np.float64)
@@ -295,6 +311,72 @@ class Grid:
 
     def last_bad_zone(self):
         return load().hog_last_bad_zone(self._h)
+
+
+class Stream:
+    """A host-resident mesh stepped through the GPU in slabs of the last axis
+    (hog_stream_*): two pinned host state buffers, one device workspace, the
+    current torch stream for compute and a second stream for the copies."""
+
+    def __init__(self, ndim, n, order, h, slab_planes, **kw):
+        import torch
+        self._torch = torch
+        self.cfg = make_config(ndim, n, order, h, **kw)
+        self.ndim, self.nv = ndim, ndim + 2
+        self.n = (self.cfg.nx, self.cfg.ny, self.cfg.nz)
+        self.shape = (self.nv, self.n[2], self.n[1], self.n[0]) if ndim == 3 else (self.nv, self.n[1], self.n[0])
+        L = load()
+        nb = C.c_size_t(0)
+        _check(L.hog_stream_workspace_size(C.byref(self.cfg), int(slab_planes), C.byref(nb)))
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.host = [torch.empty(self.shape, dtype=torch.float64, pin_memory=True) for _ in range(2)]
+        self.compute = torch.cuda.current_stream()
+        self.copy = torch.cuda.Stream()
+        h_ = C.c_void_p()
+        _check(L.hog_stream_create(C.byref(self.cfg), int(slab_planes), C.c_void_p(aligned), nb.value,
+                                   C.c_void_p(self.host[0].data_ptr()), C.c_void_p(self.host[1].data_ptr()),
+                                   C.c_void_p(self.compute.cuda_stream), C.c_void_p(self.copy.cuda_stream),
+                                   C.byref(h_)))
+        self._h = h_
+
+    @classmethod
+    def from_problem(cls, pb, order, slab_planes, **kw):
+        kw.setdefault("gamma", pb.gamma)
+        kw.setdefault("bc", pb.bc)
+        s = cls(pb.ndim, pb.n, order, pb.h, slab_planes, **kw)
+        s.host[0].copy_(s._torch.from_numpy(np.ascontiguousarray(pb.U)))
+        return s
+
+    def _current(self):
+        p = C.c_void_p()
+        _check(load().hog_stream_state(self._h, C.byref(p)))
+        return self.host[0] if p.value == self.host[0].data_ptr() else self.host[1]
+
+    def get_state(self):
+        return self._current().numpy().copy()
+
+    def compute_dt(self):
+        dt = C.c_double(0.0)
+        _check(load().hog_stream_compute_dt(self._h, C.byref(dt)))
+        return dt.value
+
+    def step(self, dt=0.0):
+        nxt = C.c_double(0.0)
+        _check(load().hog_stream_step(self._h, float(dt), C.byref(nxt)))
+        return nxt.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().hog_stream_destroy(self._h)
+            self._h = C.c_void_p()
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def param_count(ndim):

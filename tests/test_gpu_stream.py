@@ -1,0 +1,115 @@
+"""Slab streaming of a host-resident mesh (hog_stream_*) and the external
+boundary it is built on: the streamed step must equal the in-core step of the
+whole mesh zone for zone (bitwise: every zone sees the same stencil and the
+same arithmetic), over several steps with the CFL dt, and match the oracle."""
+import numpy as np
+import pytest
+
+import icgen
+import oracle
+from tests.test_gpu_parity import REL_L1, note, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hog():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_13295_amd import hog as h
+    h.load()
+    return h
+
+
+def _mesh(ndim, n, bc_last, seed):
+    bc = ["outflow", "periodic", bc_last] if ndim == 3 else ["periodic", bc_last, "outflow"]
+    pb = icgen.random_smooth(n=n, ndim=ndim, seed=seed, amp=0.3, bc="periodic", h=(0.1, 0.08, 0.11))
+    pb.bc = tuple(bc)
+    return pb
+
+
+@pytest.mark.parametrize("ndim,order", [(3, 4), (3, 2), (2, 3)])
+def test_external_slab_matches_in_core(hog, ndim, order):
+    """A slab grid whose last axis is external, given its ghost layers from the
+    mesh (periodic wrap), steps its zones exactly like the whole mesh does."""
+    n = (12, 9, 20) if ndim == 3 else (30, 20, 1)
+    note(f"external slab ndim={ndim} order={order}")
+    pb = _mesh(ndim, n, "periodic", 3)
+    g = hog.Grid.from_problem(pb, order)
+    c = oracle.cfg_from_problem(pb, order)
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    g.step(dt)
+    full = g.get_state()
+    g.close()
+    nl = n[ndim - 1]
+    z0, nz = 6, 7
+    idx = [(z0 + k) % nl for k in range(-3, nz + 3)]
+    ext = pb.U[:, idx] if True else None
+    ns = list(n)
+    ns[ndim - 1] = nz
+    bc = list(pb.bc)
+    bc[ndim - 1] = "external"
+    s = hog.Grid(ndim, ns, order, pb.h, gamma=pb.gamma, bc=tuple(bc))
+    s.set_state_ext(ext)
+    s.step(dt)
+    got = s.get_state()
+    s.close()
+    np.testing.assert_array_equal(got, full[:, z0:z0 + nz])
+
+
+CASES = [(3, 4, "periodic", (14, 11, 23), 5), (3, 3, "outflow", (13, 10, 17), 8), (3, 2, "periodic", (33, 20, 19), 3),
+         (3, 4, "outflow", (9, 8, 10), 10), (2, 4, "outflow", (40, 29, 1), 7), (2, 2, "periodic", (300, 26, 1), 1)]
+
+
+@pytest.mark.parametrize("ndim,order,bc_last,n,slab", CASES)
+def test_stream_equals_in_core(hog, ndim, order, bc_last, n, slab):
+    note(f"stream ndim={ndim} order={order} {bc_last} n={n} slab={slab}")
+    pb = _mesh(ndim, n, bc_last, order + slab)
+    riemann = "hll" if order == 2 else "hllc"
+    g = hog.Grid.from_problem(pb, order, riemann=riemann)
+    st = hog.Stream.from_problem(pb, order, slab, riemann=riemann)
+    dt_g, dt_s = g.compute_dt(), st.compute_dt()
+    assert dt_g == dt_s
+    for k in range(3):
+        dt_g = g.step(dt_g)
+        dt_s = st.step(0.0 if k else dt_s)
+        assert dt_g == dt_s
+        np.testing.assert_array_equal(st.get_state(), g.get_state())
+    g.close()
+    st.close()
+
+
+def test_stream_matches_oracle(hog):
+    note("stream 3D O4 vs oracle")
+    pb = _mesh(3, (11, 10, 13), "periodic", 5)
+    st = hog.Stream.from_problem(pb, 4, 4)
+    c = oracle.cfg_from_problem(pb, 4)
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    st.step(dt)
+    Uo = oracle.step(c, pb.U, dt)
+    assert rel_l1(st.get_state(), Uo) <= REL_L1
+    st.close()
+
+
+def test_stream_nonphysical_step_keeps_the_state(hog):
+    note("stream non-physical")
+    pb = icgen.multiblast(n=24, seed=3)
+    st = hog.Stream.from_problem(pb, 4, 5, positivity=False)
+    U0 = st.get_state()
+    with pytest.raises(hog.HogError) as e:
+        st.step(0.0)
+    assert e.value.code == hog.HOG_ENONPHYS
+    np.testing.assert_array_equal(st.get_state(), U0)
+    st.close()
+
+
+def test_stream_rejects_bad_configurations(hog):
+    pb = icgen.uniform(n=(6, 6, 6), ndim=3)
+    for kw, slab in (({"stepper": "rk3"}, 2), ({}, 0), ({}, 7), ({"bc": ("periodic", "periodic", "external")}, 2)):
+        with pytest.raises(hog.HogError) as e:
+            hog.Stream.from_problem(pb, 4, slab, **kw)
+        assert e.value.code == hog.HOG_EINVAL
+    with pytest.raises(hog.HogError) as e:
+        hog.Grid(3, (6, 6, 6), 4, (0.1, 0.1, 0.1), bc=("external", "periodic", "periodic"))
+    assert e.value.code == hog.HOG_EINVAL
