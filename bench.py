@@ -414,6 +414,53 @@ def host_round_trip(hog, torch, args):
     return out
 
 
+def stream_vs_in_core(hog, torch, args):
+    """A host-resident mesh stepped through the GPU in slabs (hog_stream_*)
+    against the same mesh in core: 256^3 3D workload, fourth order (HLLC) and
+    second order (HLL), FP64, slabs of 32 planes; the copies of one slab
+    overlap the step of the other, so the streamed rate is bounded by the
+    larger of compute and PCIe time."""
+    import icgen
+    n = 256
+    pb = icgen.vortex3d_perturbed(n=n, seed=2)
+    out = {"metric": "zone-updates/s, host-resident mesh streamed in slabs vs in core", "unit": UNIT, "n_gpus": 1,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"3D vortex + density modes, {n}^3 periodic, FP64, CFL 0.4, slabs of 32 planes"},
+           "rows": []}
+    for order, riemann, steps in ((4, "hllc", 5), (2, "hll", 20)):
+        g = hog.Grid.from_problem(pb, order, riemann=riemann)
+        dt = g.compute_dt()
+        g.advance(2)
+        g.set_state(pb.U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.advance(steps)
+        torch.cuda.synchronize()
+        t_in = (time.perf_counter() - t0) / steps
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+        st = hog.Stream.from_problem(pb, order, 32, riemann=riemann)
+        st.step(dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st.step(0.0)
+        t_st = (time.perf_counter() - t0) / steps
+        st.close()
+        del st
+        torch.cuda.empty_cache()
+        nbytes = n ** 3 * 5 * 8
+        moved = nbytes * (1 + 6 / 32) + nbytes           # slabs with ghost layers in, interiors out
+        row = {"order": order, "riemann": riemann, "steps": steps, "slab_planes": 32,
+               "in_core_zone_updates_per_s": n ** 3 / t_in, "in_core_ms_per_step": t_in * 1e3,
+               "streamed_zone_updates_per_s": n ** 3 / t_st, "streamed_ms_per_step": t_st * 1e3,
+               "bytes_moved_per_step": moved, "pcie_GBps_if_transfer_bound": moved / t_st / 1e9}
+        out["rows"].append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(order, seconds):
     """The CPU oracle (plain FP64 C, OpenMP over zones) timed on this host on a
     bounded sample: whole steps of the same 3D workload at 32^3 (per-zone work
@@ -682,6 +729,9 @@ def main():
     ap.add_argument("--host-round-trip", action="store_true",
                     help="instead of the benchmark line: steps with the paper's per-step host round trip of the "
                          "zone means vs the resident loop; prints one JSON line")
+    ap.add_argument("--stream", action="store_true",
+                    help="instead of the benchmark line: a host-resident 256^3 mesh streamed through the GPU in "
+                         "slabs vs in core; prints one JSON line")
     ap.add_argument("--ader-vs-rk", action="store_true",
                     help="instead of the benchmark line: ADER vs Runge-Kutta throughput at orders 2-4 (Table IV); "
                          "prints one JSON line")
@@ -724,6 +774,9 @@ def main():
         return
     if args.host_round_trip:
         print(json.dumps(host_round_trip(hog, torch, args)), flush=True)
+        return
+    if args.stream:
+        print(json.dumps(stream_vs_in_core(hog, torch, args)), flush=True)
         return
     if args.shock_workload:
         steps = 100 if args.shock_workload == "multiblast256" else 200

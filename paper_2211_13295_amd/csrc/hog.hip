@@ -1215,7 +1215,7 @@ struct hog_stream {
     long long plane, nmesh;        // zones per plane of the last axis; zones of the mesh
     double* host[2];               // pinned, caller-owned: current / next state, SoA [v][nlast][plane]
     int cur;
-    hipStream_t cs, xs;
+    hipStream_t cs, xs, xo;        // compute, copy in (caller's), copy out (own, default priority)
     hog_grid* g[3];                // slab grids: two of pn planes, one for a shorter last slab
     double* in[2];                 // device staging, [v][pn + 6][plane]
     double* out[2];                // device staging, [v][pn][plane]
@@ -1358,8 +1358,10 @@ int hog_stream_create(const hog_config* mesh, int slab_planes, void* workspace, 
     s->last_bad = -1;
     for (int k = 0; k < 3; ++k) s->g[k] = nullptr;
     for (int k = 0; k < 2; ++k) s->h2d[k] = s->comp[k] = s->done[k] = nullptr;
+    s->xo = nullptr;
     auto cleanup = [&](int code) {
         for (int k = 0; k < 3; ++k) hog_destroy(s->g[k]);
+        if (s->xo) (void)hipStreamDestroy(s->xo);
         for (int k = 0; k < 2; ++k) {
             if (s->h2d[k]) (void)hipEventDestroy(s->h2d[k]);
             if (s->comp[k]) (void)hipEventDestroy(s->comp[k]);
@@ -1373,6 +1375,8 @@ int hog_stream_create(const hog_config* mesh, int slab_planes, void* workspace, 
         rc = hog_create(k == 2 ? &S.tcfg : &S.pcfg, ws + S.off_g[k], S.bytes_g[k], compute_stream, &s->g[k]);
         if (rc) return cleanup(rc);
     }
+    if (hipStreamCreateWithFlags(&s->xo, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(fail(HOG_EDEVICE, "stream creation failed"));
     for (int k = 0; k < 2; ++k) {
         s->in[k] = reinterpret_cast<double*>(ws + S.off_in[k]);
         s->out[k] = reinterpret_cast<double*>(ws + S.off_out[k]);
@@ -1392,12 +1396,14 @@ int hog_stream_destroy(hog_stream* s)
     if (!s) return HOG_OK;
     (void)hipStreamSynchronize(s->cs);
     (void)hipStreamSynchronize(s->xs);
+    (void)hipStreamSynchronize(s->xo);
     for (int k = 0; k < 3; ++k) hog_destroy(s->g[k]);
     for (int k = 0; k < 2; ++k) {
         (void)hipEventDestroy(s->h2d[k]);
         (void)hipEventDestroy(s->comp[k]);
         (void)hipEventDestroy(s->done[k]);
     }
+    (void)hipStreamDestroy(s->xo);
     delete s;
     return HOG_OK;
 }
@@ -1411,16 +1417,29 @@ int hog_stream_state(hog_stream* s, double** host_state)
 
 // One pass over the slabs: with step = 0 the CFL reduction of the current
 // state, else one step of every slab with dt, new state into the other buffer.
+// Software pipeline: the copy-in of slab p+1 is queued before slab p is
+// computed, and the copy-out of slab p runs on its own stream, so both PCIe
+// directions overlap the computation of the neighbouring slabs.
 static int stream_pass(hog_stream* s, double dt, int step)
 {
+    auto copy_in = [&](int p) -> int {
+        const int slot = p & 1;
+        HIP_TRY(hipStreamWaitEvent(s->xs, s->done[slot], 0));   // slot free: slab p-2 copied out
+        int rc = stream_h2d(s, p, slot);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(s->h2d[slot], s->xs));
+        return HOG_OK;
+    };
+    int rc = copy_in(0);
+    if (rc) return rc;
     for (int p = 0; p < s->npatch; ++p) {
         const int slot = p & 1;
         const int z0 = p * s->pn, np = std::min(s->pn, s->nlast - z0);
         hog_grid* g = (np == s->pn) ? s->g[slot] : s->g[2];
-        HIP_TRY(hipStreamWaitEvent(s->xs, s->done[slot], 0));
-        int rc = stream_h2d(s, p, slot);
-        if (rc) return rc;
-        HIP_TRY(hipEventRecord(s->h2d[slot], s->xs));
+        if (p + 1 < s->npatch) {
+            rc = copy_in(p + 1);
+            if (rc) return rc;
+        }
         HIP_TRY(hipStreamWaitEvent(s->cs, s->h2d[slot], 0));
         rc = stream_pack(s, g, slot);
         if (rc) return rc;
@@ -1440,17 +1459,18 @@ static int stream_pass(hog_stream* s, double dt, int step)
         rc = launch_check("slab step");
         if (rc) return rc;
         HIP_TRY(hipEventRecord(s->comp[slot], s->cs));
-        HIP_TRY(hipStreamWaitEvent(s->xs, s->comp[slot], 0));
+        HIP_TRY(hipStreamWaitEvent(s->xo, s->comp[slot], 0));
         if (step) {
             const size_t bytes = sizeof(double) * (size_t)np * s->plane;
             for (int v = 0; v < s->nv; ++v)
                 HIP_TRY(hipMemcpyAsync(s->host[s->cur ^ 1] + ((long long)v * s->nlast + z0) * s->plane,
-                                       s->out[slot] + (long long)v * np * s->plane, bytes, hipMemcpyDeviceToHost, s->xs));
+                                       s->out[slot] + (long long)v * np * s->plane, bytes, hipMemcpyDeviceToHost, s->xo));
         }
-        HIP_TRY(hipEventRecord(s->done[slot], s->xs));
+        HIP_TRY(hipEventRecord(s->done[slot], s->xo));
     }
     HIP_TRY(hipStreamSynchronize(s->cs));
     HIP_TRY(hipStreamSynchronize(s->xs));
+    HIP_TRY(hipStreamSynchronize(s->xo));
     return HOG_OK;
 }
 
