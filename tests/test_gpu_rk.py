@@ -149,3 +149,31 @@ def test_rk_rejects_what_it_does_not_run(hog):
         g.set_gate_flags(np.zeros((6, 6, 6), dtype=np.uint8))
     assert e.value.code == hog.HOG_EINVAL
     g.close()
+
+
+def test_rk_full_size_first_step_sampled(hog):
+    """128^3 fourth-order five-stage step of the 3D workload in the benchmark's
+    launch configuration.  A Runge-Kutta zone depends on the zones within 3 per
+    stage (reconstruction radius 2 plus the face neighbour), 15 for five stages:
+    the oracle computes each sampled zone on the periodic cut-out of half-width
+    20 around it (outflow at the cut, 5 zones beyond the reach)."""
+    note("RK4 O4 vortex3d_perturbed 128^3 first step, sampled")
+    n, r = 128, 20
+    pb = icgen.vortex3d_perturbed(n=n, seed=2)
+    g = hog.Grid.from_problem(pb, 4, stepper="rk4")
+    c = oracle.cfg_from_problem(pb, 4, stepper="rk4")
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    g.step(dt)
+    U = g.get_state()
+    g.close()
+    rng = np.random.default_rng(3)
+    pts = np.vstack([rng.integers(0, n, size=(3, 3)), [[0, 0, 0], [127, 64, 1]]])
+    m = 2 * r + 1
+    cut = oracle.make_cfg(3, (m, m, m), 4, pb.h, gamma=pb.gamma, bc=("outflow",) * 3, stepper="rk4")
+    for i, j, k in pts:
+        ix = [(i + d) % n for d in range(-r, r + 1)]
+        jx = [(j + d) % n for d in range(-r, r + 1)]
+        kx = [(k + d) % n for d in range(-r, r + 1)]
+        sub = pb.U[:, kx][:, :, jx][:, :, :, ix]
+        ref = oracle.step(cut, sub, dt)[:, r, r, r]
+        np.testing.assert_allclose(U[:, k, j, i], ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())

@@ -198,3 +198,28 @@ def test_rk_positivity_fallback_on_the_blast():
     assert hits > 0
     tot0, tot1 = pb.U.sum(axis=(1, 2, 3)), U.sum(axis=(1, 2, 3))
     assert (np.abs(tot1 - tot0) / np.maximum(np.abs(pb.U).sum(axis=(1, 2, 3)), 1.0)).max() < 1e-13
+
+
+def test_rk_step_depends_on_zones_within_the_stage_reach():
+    """Five stages of third/fourth-order reconstruction reach 3 zones each: the
+    step at a zone computed on a periodic cut-out of half-width 17 (outflow at
+    the cut) equals the whole-mesh step there; with half-width 13 the cut is
+    inside the reach and the result differs."""
+    n = 40
+    pb = icgen.vortex3d_perturbed(n=n, seed=2)
+    c = oracle.cfg_from_problem(pb, 4, stepper="rk4")
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    full = oracle.step(c, pb.U, dt)
+    i, j, k = 3, 21, 38
+    for r, same in ((17, True), (13, False)):
+        ix = [(i + d) % n for d in range(-r, r + 1)]
+        jx = [(j + d) % n for d in range(-r, r + 1)]
+        kx = [(k + d) % n for d in range(-r, r + 1)]
+        sub = pb.U[:, kx][:, :, jx][:, :, :, ix]
+        m = 2 * r + 1
+        cut = oracle.make_cfg(3, (m, m, m), 4, pb.h, gamma=pb.gamma, bc=("outflow",) * 3, stepper="rk4")
+        got = oracle.step(cut, sub, dt)[:, r, r, r]
+        if same:
+            np.testing.assert_array_equal(got, full[:, k, j, i])
+        else:
+            assert np.abs(got - full[:, k, j, i]).max() > 0.0
