@@ -31,9 +31,11 @@ UNIT = "zone-updates/s"
 PEAK_FP64_VALU_TFLOPS = 78.6          # MI355X published FP64 vector peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_predictor_vortex3d_128.json")
 TRAFFIC_FILE_O2 = os.path.join(ROOT, "profiles", "traffic_o2_step_vortex3d_128.json")
+TRAFFIC_FILE_RK = os.path.join(ROOT, "profiles", "traffic_face_points_vortex3d_128.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2211_13295_amd", "csrc", f)
                   for f in ("hog_kernels.h", "hog_physics.h", "hog_tables.h")]
 KERNEL_SOURCES_O2 = KERNEL_SOURCES + [os.path.join(ROOT, "paper_2211_13295_amd", "csrc", "hog_o2.h")]
+KERNEL_SOURCES_RK = KERNEL_SOURCES + [os.path.join(ROOT, "paper_2211_13295_amd", "csrc", "hog_rk.h")]
 
 
 def _binom(n, k):
@@ -142,11 +144,14 @@ def kernel_hash(sources=KERNEL_SOURCES):
     return h.hexdigest()[:16]
 
 
-def traffic_record(second_order=False):
-    """HBM bytes per launch of the dominant kernel (the predictor, or the fused
-    second-order kernel) measured with rocprofv3 counters, if the kernel
-    sources have not changed since they were taken."""
+def traffic_record(second_order=False, kind=None):
+    """HBM bytes per launch of the dominant kernel (the predictor, the fused
+    second-order kernel, or with kind="rk" the Runge-Kutta face-point kernel)
+    measured with rocprofv3 counters, if the kernel sources have not changed
+    since they were taken."""
     path, src = (TRAFFIC_FILE_O2, KERNEL_SOURCES_O2) if second_order else (TRAFFIC_FILE, KERNEL_SOURCES)
+    if kind == "rk":
+        path, src = TRAFFIC_FILE_RK, KERNEL_SOURCES_RK
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -160,18 +165,23 @@ def traffic_record(second_order=False):
 PMC_COMMAND = ("export TMPDIR=/tmp; timeout -s KILL 240 rocprofv3 --pmc {ctr} --kernel-include-regex "
                "\"k_predict|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --steps 2 "
                "--warmup 0 --no-cpu-baseline --no-mixed --copy-calibration")
+PMC_COMMAND_RK = ("export TMPDIR=/tmp; timeout -s KILL 300 rocprofv3 --pmc {ctr} --kernel-include-regex "
+                  "\"k_face_points|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py "
+                  "--ader-vs-rk --steps 1 --copy-calibration")
 PMC_COMMAND_O2 = ("export TMPDIR=/tmp; timeout -s KILL 240 rocprofv3 --pmc {ctr} --kernel-include-regex "
                   "\"k_o2_step|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py "
                   "--second-order --steps 3 --warmup 0 --no-cpu-baseline --copy-calibration")
 
 
-def write_traffic(fetch_csv, write_csv, n=128, second_order=False):
+def write_traffic(fetch_csv, write_csv, n=128, second_order=False, kind=None):
     """Traffic record of the FP64 predictor (or of the fused second-order
     kernel) from two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB
     per dispatch) of this script with --copy-calibration: each counter is
     scaled by what it reads for the plain copy of 2^27 doubles (1 GiB read,
     1 GiB written) in the same run."""
     kname = "k_o2_step<3" if second_order else "k_predict<3, 3, double>"
+    if kind == "rk":
+        kname = "k_face_points<3, 3>"
     import csv
     from collections import defaultdict
 
@@ -194,6 +204,25 @@ def write_traffic(fetch_csv, write_csv, n=128, second_order=False):
     fetch, fcopy = per_dispatch(fetch_csv, "FETCH_SIZE")
     write, wcopy = per_dispatch(write_csv, "WRITE_SIZE")
     fs, ws = gib / fcopy, gib / wcopy
+    if kind == "rk":
+        rec = {
+            "kernel": "k_face_points<3, 3> (Runge-Kutta face points, fourth order, FP64)",
+            "workload": f"3D vortex + density modes, {n}^3, order 4, SSP-RK(5,4)",
+            "kernel_hash": kernel_hash(KERNEL_SOURCES_RK),
+            "bytes_per_launch": fetch * fs + write * ws,
+            "fetch_bytes_per_launch": fetch * fs,
+            "write_bytes_per_launch": write * ws,
+            "fetch_scale": fs,
+            "write_scale": ws,
+            "algorithmic_bytes_per_launch": (n + 2) ** 3 * (20 + 24) * 5 * 8,
+            "commands": [PMC_COMMAND_RK.format(ctr="FETCH_SIZE", tag="rkfetch"),
+                         PMC_COMMAND_RK.format(ctr="WRITE_SIZE", tag="rkwrite")],
+            "calibration": "plain elementwise copy of 2^27 doubles (1 GiB read + 1 GiB written) in the same runs",
+        }
+        with open(TRAFFIC_FILE_RK, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec, indent=1))
+        return
     if second_order:
         rec = {
             "kernel": "k_o2_step<3, HLL> (fused second-order step, FP64)",
@@ -355,7 +384,8 @@ def ader_vs_rk(hog, torch, args):
             t = row["rk"]["stage_ms_per_step"]["predictor"] / nst / 1e3
             row["rk"]["roofline"] = {"bound": "hbm", "kernel": f"k_face_points<3, {order - 1}>",
                                      "achieved": alg / t / 1e9, "peak": 8000.0, "unit": "GB/s",
-                                     "frac": alg / t / 8e12, "traffic": None,
+                                     "frac": alg / t / 8e12,
+                                     "traffic": traffic_record(kind="rk") if order == 4 else None,
                                      "alg_bytes_per_launch": alg, "avg_launch_ms": t * 1e3}
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
@@ -739,7 +769,7 @@ def main():
                     help="write the predictor traffic record from two rocprofv3 counter files and exit")
     args = ap.parse_args()
     if args.traffic_from:
-        write_traffic(*args.traffic_from, second_order=args.second_order)
+        write_traffic(*args.traffic_from, second_order=args.second_order, kind="rk" if args.ader_vs_rk else None)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU path (halo exchange and a min "
