@@ -191,7 +191,10 @@ int hog_debug_tap(hog_grid* g, int tap, void* dst, size_t bytes);
 /* Stage timing with HIP events recorded on the handle's stream around every
  * stage of every subsequent step: 0 ghost fill, 1 reconstruction sweeps,
  * 2 ADER predictor, 3 Riemann solver, 4 update + CFL, 5 learned-gate
- * inference (only with a gate set) (HOG_NSTAGES).  Used to
+ * inference (only with a gate set) (HOG_NSTAGES).  At order 2 the fused
+ * kernel is recorded as stage 2; with Runge-Kutta stepping stage 2 holds the
+ * face-point evaluation (or the fused kernel at order 2) and stage 4 the
+ * stage combination, summed over the stages of a step.  Used to
  * split step time the way the paper splits out the predictor (Sec. III.1,
  * Table III).  enable = 0 stops recording.  Errors: HOG_EINVAL, HOG_EDEVICE. */
 #define HOG_NSTAGES 6
@@ -205,7 +208,8 @@ int hog_profile_read(hog_grid* g, double* ms, int* launches, int nstages);
 /* Device-side counters of the last step (synchronises): *t time advanced
  * since the last hog_advance/hog_set_state, *dt the last time step,
  * *fallback_zones the predictor zones (interior grown by one zone per axis)
- * that used the positivity fallback in the last step.  Pointers may be NULL.
+ * that used the positivity fallback in the last step (summed over the stages
+ * of a Runge-Kutta step).  Pointers may be NULL.
  * Errors: HOG_EINVAL, HOG_EDEVICE. */
 int hog_stats(hog_grid* g, double* t, double* dt, long long* fallback_zones);
 
