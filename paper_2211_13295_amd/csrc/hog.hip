@@ -318,7 +318,7 @@ int enqueue_step_t(hog_grid* g, double dt_user)
     return launch_check("step");
 }
 
-// Planes of the march axis per workgroup of the second-order kernel.  Two
+// Planes of the march axis per workgroup of the second-order kernel.  MINB
 // workgroups are resident per compute unit; the march is cut into as many
 // chunks as fill whole rounds of resident workgroups (a partial last round
 // leaves compute units idle), using as few rounds as keep the chunks at about
@@ -330,7 +330,7 @@ int o2_chunk(const Plan& L, int cus)
     const long long cols = (long long)((L.n[0] + S::TX - 3) / (S::TX - 2)) *
                            (D == 3 ? (L.n[1] + S::TY - 3) / (S::TY - 2) : 1);
     const long long nm = L.n[D - 1];
-    const long long slots = 2ll * cus;
+    const long long slots = (long long)S::MINB * cus;
     const long long rounds = std::max(1ll, (nm * cols + slots * 32 - 1) / (slots * 32));
     const long long chunks = std::max(1ll, rounds * slots / cols);
     return (int)std::min(nm, (nm + chunks - 1) / chunks);

@@ -13,7 +13,8 @@
 // (periodic wrap or zero-gradient clamp of the zone index), so the padded
 // ghost layers are never read or written.
 //
-// Thread layout: a TX x TY grid of zone columns (3D: x, y; 2D: x only) whose
+// Thread layout: a TX x TY grid of zone columns (3D: 32 x 16, one workgroup of
+// 8 wavefronts per compute unit; 2D: a row of 256, two per compute unit) whose
 // outer ring is a halo of one zone (its modes are needed for the faces of the
 // tile); the tile proper is the (TX-2) x (TY-2) inner part.  Per plane of the
 // march axis a thread computes the modes of its zone, hands its +x / +y face
@@ -26,8 +27,23 @@
 namespace hog {
 
 template <int D> struct O2Shape;
-template <> struct O2Shape<3> { static constexpr int TX = 16, TY = 16; };
-template <> struct O2Shape<2> { static constexpr int TX = 256, TY = 1; };
+template <> struct O2Shape<3> { static constexpr int TX = 32, TY = 16, NT = 512, MINB = 1; };
+template <> struct O2Shape<2> { static constexpr int TX = 256, TY = 1, NT = 256, MINB = 2; };
+
+// Block max of the signal speed (up to 16 wavefronts) and one 64-bit atomic max.
+__device__ __forceinline__ void o2_block_max(double s, StepInfo* info)
+{
+    __shared__ double red[16];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s = fmax(s, __shfl_xor(s, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q) b = fmax(b, red[q]);
+        atomicMax(&info->smax_bits, (unsigned long long)__double_as_longlong(b));
+    }
+}
 
 // Monotonised-central limiter with a compression factor (Fig. 3), from the
 // forward difference a and the backward difference b: 0 unless both have the
@@ -118,7 +134,7 @@ struct O2Taps {
 // RK: a Runge-Kutta stage -- no time mode, and instead of the new state the
 // kernel writes dt L of the interior zones to Lout ([v][zone], x fastest).
 template <int D, int SOLVER, bool TAPS, bool RK>
-__global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ Uo, double* __restrict__ Un, Pad p,
+__global__ __launch_bounds__(O2Shape<D>::NT, O2Shape<D>::MINB) void k_o2_step(const double* __restrict__ Uo, double* __restrict__ Un, Pad p,
                                                  O2Args a, StepInfo* info, O2Taps tp, double* __restrict__ Lout)
 {
     using Sh = O2Shape<D>;
@@ -380,7 +396,7 @@ __global__ __launch_bounds__(256, 2) void k_o2_step(const double* __restrict__ U
         }
     }
     if (a.positivity && nfb) atomicAdd(&info->fallback, nfb);
-    if constexpr (!RK) cfl_reduce<D>(smax, true, 0, info);
+    if constexpr (!RK) o2_block_max(smax, info);
 }
 
 } // namespace hog
