@@ -80,6 +80,26 @@ def test_stream_equals_in_core(hog, ndim, order, bc_last, n, slab):
     st.close()
 
 
+@pytest.mark.parametrize("ndim,n,slab", [(3, (14, 11, 23), 5), (2, (40, 29, 1), 7)])
+def test_stream_mixed_precision_equals_in_core(hog, ndim, n, slab):
+    """The mixed FP32/FP64 path streams too: same kernels per slab, so the
+    streamed steps equal the in-core mixed steps bitwise."""
+    note(f"stream mixed ndim={ndim} n={n} slab={slab}")
+    pb = _mesh(ndim, n, "periodic", 11)
+    g = hog.Grid.from_problem(pb, 4, precision="mixed")
+    st = hog.Stream.from_problem(pb, 4, slab, precision="mixed")
+    dt = g.compute_dt()
+    assert st.compute_dt() == dt
+    for k in range(2):
+        dt_g = g.step(dt)
+        dt_s = st.step(dt)
+        assert dt_g == dt_s
+        dt = dt_g
+        np.testing.assert_array_equal(st.get_state(), g.get_state())
+    g.close()
+    st.close()
+
+
 def test_stream_matches_oracle(hog):
     note("stream 3D O4 vs oracle")
     pb = _mesh(3, (11, 10, 13), "periodic", 5)
