@@ -236,7 +236,7 @@ int hog_stream_workspace_size(const hog_config* mesh, int slab_planes, size_t* b
  * borrowed), two host buffers of nv*nx*ny*nz doubles each (SoA [v][nz][ny][nx];
  * pinned host memory, e.g. hipHostMalloc or a pinned torch tensor; borrowed;
  * host_a holds the initial state, host_b receives the next one and the two
- * alternate) and two different HIP streams (compute and copy).
+ * alternate; they must not overlap) and two different HIP streams (compute and copy).
  * Errors: HOG_EINVAL, HOG_ENOMEM (workspace too small), HOG_EDEVICE. */
 int hog_stream_create(const hog_config* mesh, int slab_planes, void* workspace, size_t bytes, double* host_a,
                       double* host_b, void* compute_stream, void* copy_stream, hog_stream** out);

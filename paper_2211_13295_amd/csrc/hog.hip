@@ -1333,6 +1333,7 @@ int hog_stream_create(const hog_config* mesh, int slab_planes, void* workspace, 
     if (!out || !host_a || !host_b || !workspace) return fail(HOG_EINVAL, "NULL argument");
     *out = nullptr;
     if (compute_stream == copy_stream) return fail(HOG_EINVAL, "the compute and copy streams must differ");
+    if (host_a == host_b) return fail(HOG_EINVAL, "the two host state buffers must differ");
     StreamPlan S;
     int rc = stream_plan(mesh, slab_planes, &S);
     if (rc) return rc;

@@ -207,7 +207,13 @@ class Grid:
 
     def set_state_ext(self, U):
         """Interior plus the three ghost layers below and above along an
-        external last axis: SoA [v][n_last + 6][...] (host array)."""
+        external last axis: SoA [v][n_last + 6][...] (host array or CUDA tensor)."""
+        torch = self._torch
+        if isinstance(U, torch.Tensor) and U.is_cuda:
+            t = U.contiguous().to(torch.float64)
+            _check(load().hog_set_state_ext(self._h, C.c_void_p(t.data_ptr()), DEVICE))
+            torch.cuda.current_stream().synchronize()
+            return
         a = np.ascontiguousarray(U, dtype=np.float64)
         _check(load().hog_set_state_ext(self._h, a.ctypes.data_as(C.c_void_p), HOST))
 

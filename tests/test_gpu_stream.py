@@ -45,17 +45,19 @@ def test_external_slab_matches_in_core(hog, ndim, order):
     nl = n[ndim - 1]
     z0, nz = 6, 7
     idx = [(z0 + k) % nl for k in range(-3, nz + 3)]
-    ext = pb.U[:, idx] if True else None
+    ext = pb.U[:, idx]
     ns = list(n)
     ns[ndim - 1] = nz
     bc = list(pb.bc)
     bc[ndim - 1] = "external"
-    s = hog.Grid(ndim, ns, order, pb.h, gamma=pb.gamma, bc=tuple(bc))
-    s.set_state_ext(ext)
-    s.step(dt)
-    got = s.get_state()
-    s.close()
-    np.testing.assert_array_equal(got, full[:, z0:z0 + nz])
+    import torch
+    for src in (ext, torch.from_numpy(np.ascontiguousarray(ext)).cuda()):     # host, then device
+        s = hog.Grid(ndim, ns, order, pb.h, gamma=pb.gamma, bc=tuple(bc))
+        s.set_state_ext(src)
+        s.step(dt)
+        got = s.get_state()
+        s.close()
+        np.testing.assert_array_equal(got, full[:, z0:z0 + nz])
 
 
 CASES = [(3, 4, "periodic", (14, 11, 23), 5), (3, 3, "outflow", (13, 10, 17), 8), (3, 2, "periodic", (33, 20, 19), 3),
@@ -133,6 +135,24 @@ def test_stream_rejects_bad_configurations(hog):
     with pytest.raises(hog.HogError) as e:
         hog.Grid(3, (6, 6, 6), 4, (0.1, 0.1, 0.1), bc=("external", "periodic", "periodic"))
     assert e.value.code == hog.HOG_EINVAL
+    # one host buffer for both states, or one stream for compute and copies
+    import ctypes
+    import torch
+    L = hog.load()
+    cfg = hog.make_config(3, (6, 6, 6), 4, (0.1, 0.1, 0.1))
+    nb = ctypes.c_size_t(0)
+    assert L.hog_stream_workspace_size(ctypes.byref(cfg), 3, ctypes.byref(nb)) == hog.HOG_OK
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    wp = ctypes.c_void_p((ws.data_ptr() + 255) // 256 * 256)
+    host = torch.empty((5, 6, 6, 6), dtype=torch.float64, pin_memory=True)
+    other = torch.empty_like(host).pin_memory()
+    cs, xs = torch.cuda.current_stream(), torch.cuda.Stream()
+    out = ctypes.c_void_p()
+    hp, op = ctypes.c_void_p(host.data_ptr()), ctypes.c_void_p(other.data_ptr())
+    assert L.hog_stream_create(ctypes.byref(cfg), 3, wp, nb.value, hp, hp, ctypes.c_void_p(cs.cuda_stream),
+                               ctypes.c_void_p(xs.cuda_stream), ctypes.byref(out)) == hog.HOG_EINVAL
+    assert L.hog_stream_create(ctypes.byref(cfg), 3, wp, nb.value, hp, op, ctypes.c_void_p(cs.cuda_stream),
+                               ctypes.c_void_p(cs.cuda_stream), ctypes.byref(out)) == hog.HOG_EINVAL
 
 
 def test_stream_full_size_equals_in_core(hog):
