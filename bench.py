@@ -831,6 +831,16 @@ def main():
     zones = n ** 3
     value = zones * args.steps / elapsed
     ms_step = elapsed * 1e3 / args.steps
+    # run-to-run spread: four more timed runs of the same K steps from the same state
+    reps = [ms_step]
+    for _ in range(4):
+        g.set_state(pb.U)
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        g.advance(args.steps)
+        torch.cuda.synchronize()
+        reps.append((time.perf_counter() - r0) * 1e3 / args.steps)
+    reps_sorted = sorted(reps)
 
     D, P = 3, order - 1
     zones_per_launch = (n + 2) ** 3                       # predictor runs on the interior grown by one zone
@@ -856,6 +866,8 @@ def main():
                      "alg_flops_per_zone": predictor_flops(D, P), "zones_per_launch": zones_per_launch,
                      "avg_launch_ms": avg_s * 1e3},
         "stages_ms_per_launch": stage_ms,
+        "repeats_ms_per_step": {"n": len(reps), "median": reps_sorted[len(reps) // 2], "min": reps_sorted[0],
+                                "max": reps_sorted[-1]},
         "predictor_fraction_of_step": prof["predictor"][0] / args.steps / step_sum if step_sum > 0 else None,
     }
     if not args.no_mixed:
