@@ -773,7 +773,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the multi-GPU path (halo exchange and a min "
-              "all-reduce of dt) is a design note, not part of this build.", file=sys.stderr)
+              "all-reduce of dt) is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
