@@ -25,6 +25,11 @@
  * predictor with tensor Gauss-Legendre L2 projection, 2-point Gauss face
  * quadrature in the face directions and in time).
  *
+ * Besides the one-step ADER update, the oracle takes the Runge-Kutta steppers
+ * the paper compares against (Sec. I.1, Table IV): the same reconstruction and
+ * Riemann solver per stage with face points in space only, combined in
+ * Shu-Osher form (rk_step below).
+ *
  * Everything is written in the most direct form: polynomials are evaluated
  * mode by mode, projections are sums over all quadrature nodes, and the
  * derivative / time-integral maps are applied term by term.  No blocking,
