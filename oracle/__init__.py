@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-RIEMANN = {"hllc": 0, "hll": 1, "rusanov": 2}
+RIEMANN = {"hllc": 0, "hll": 1, "rusanov": 2, "hllem": 3, "hlli": 4}
 STEPPER = {"ader": 0, "rk2": 2, "rk3": 3, "rk4": 4}
 BC = {"periodic": 0, "outflow": 1}
 

@@ -54,7 +54,7 @@ typedef struct {
     int ndim;          /* 2 or 3 */
     int nx, ny, nz;    /* interior zones; nz = 1 in 2D */
     int order;         /* 2 (the scheme of Figs. 3-7), 3 or 4: polynomial degree p = order - 1 */
-    int riemann;       /* 0 HLLC, 1 HLL, 2 Rusanov */
+    int riemann;       /* 0 HLLC, 1 HLL, 2 Rusanov, 3 HLLEM, 4 HLLI */
     int bc[3];         /* per axis: 0 periodic, 1 outflow (zero gradient) */
     int linear_weno;   /* 1: nonlinear weights replaced by the linear ones */
     int positivity;    /* 1: first-order fallback in zones with an inadmissible predicted state */
@@ -238,11 +238,45 @@ void oracle_riemann(const ocfg *c, int dir, const double *UL, const double *UR, 
     double SL = fmin(uL - cL, ut_n - ct);
     double SR = fmax(uR + cR, ut_n + ct);
 
-    if (c->riemann == 1) { /* HLL */
+    if (c->riemann == 1 || c->riemann == 3 || c->riemann == 4) { /* HLL, HLLEM, HLLI */
         if (SL >= 0.0) { for (int v = 0; v < nv; ++v) F[v] = FL[v]; return; }
         if (SR <= 0.0) { for (int v = 0; v < nv; ++v) F[v] = FR[v]; return; }
         for (int v = 0; v < nv; ++v)
             F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) / (SR - SL);
+        if (c->riemann == 1) return;
+        /* HLLEM (Einfeldt) and HLLI (Dumbser and Balsara): the HLL flux minus
+         * part of its dissipation in the linearly degenerate fields (the
+         * entropy wave and the nd-1 shear waves).  The jump is split on the
+         * right eigenvectors of Roe's matrix: with Roe velocity ut, enthalpy
+         * Ht and sound speed ct,
+         *   entropy wave  r = (1, ut, |ut|^2/2),
+         *                 alpha = (g-1)/ct^2 (drho (Ht - |ut|^2) + ut . dm - dE),
+         *   shear wave t  r = (0, e_t, ut_t),  alpha = dm_t - ut_t drho,
+         * the rows of the inverse eigenvector matrix that belong to these
+         * fields.  The anti-diffusion factor delta in [0, 1] is
+         *   HLLEM: ct / (ct + |ut_n|)                (1 for a resting contact),
+         *   HLLI:  1 - min(ut_n, 0)/SL - max(ut_n, 0)/SR
+         * (an isolated contact moving at ut_n is then resolved exactly). */
+        double ut[3], dU[MAXV];
+        for (int d = 0; d < nd; ++d) ut[d] = (sL * UL[1 + d] / rL + sR * UR[1 + d] / rR) / (sL + sR);
+        for (int v = 0; v < nv; ++v) dU[v] = UR[v] - UL[v];
+        double udm = 0.0;
+        for (int d = 0; d < nd; ++d) udm += ut[d] * dU[1 + d];
+        double a_e = (g - 1.0) / (ct * ct) * (dU[0] * (Ht - vel2) + udm - dU[nv - 1]);
+        double proj[MAXV];
+        proj[0] = a_e;
+        for (int d = 0; d < nd; ++d) proj[1 + d] = a_e * ut[d];
+        proj[nv - 1] = a_e * 0.5 * vel2;
+        for (int d = 0; d < nd; ++d) {
+            if (d == dir) continue;
+            double a_t = dU[1 + d] - ut[d] * dU[0];
+            proj[1 + d] += a_t;
+            proj[nv - 1] += a_t * ut[d];
+        }
+        double delta = (c->riemann == 3) ? ct / (ct + fabs(ut_n))
+                                         : 1.0 - fmin(ut_n, 0.0) / SL - fmax(ut_n, 0.0) / SR;
+        double k = SL * SR / (SR - SL) * delta;
+        for (int v = 0; v < nv; ++v) F[v] -= k * proj[v];
         return;
     }
     /* HLLC (Toro, Spruce and Speares): contact speed and star states. */
