@@ -62,7 +62,11 @@ enum {
  * above the interior along that axis with hog_set_state_ext, e.g. from the
  * neighbouring slabs of a larger mesh (see hog_stream_*). */
 enum { HOG_PERIODIC = 0, HOG_OUTFLOW = 1, HOG_EXTERNAL = 2 };
-enum { HOG_HLLC = 0, HOG_HLL = 1, HOG_RUSANOV = 2 };   /* Riemann solver */
+/* Riemann solver.  HOG_HLLEM and HOG_HLLI: the HLL flux with the dissipation
+ * of the entropy and shear waves of Roe's linearisation reduced by Einfeldt's
+ * factor c/(c+|u_n|) (HLLEM) or by Dumbser and Balsara's factor
+ * 1 - min(u_n,0)/S_L - max(u_n,0)/S_R (HLLI); all Roe-averaged. */
+enum { HOG_HLLC = 0, HOG_HLL = 1, HOG_RUSANOV = 2, HOG_HLLEM = 3, HOG_HLLI = 4 };
 /* Arithmetic of the path.  HOG_FP64: everything in FP64.  HOG_MIXED: the
  * reconstruction coefficients, predictor, face states and Riemann solver in
  * FP32; the stencil differences, smoothness indicators, epsilon division and
@@ -99,7 +103,7 @@ typedef struct hog_config {
     int nx, ny, nz;      /* interior zones per axis (nz = 1 in 2D), each >= 1 */
     int order;           /* 2, 3 or 4 (polynomial degree p = order - 1); 2 is the
                             scheme of Figs. 3-7 and needs precision HOG_FP64 */
-    int riemann;         /* HOG_HLLC | HOG_HLL | HOG_RUSANOV */
+    int riemann;         /* HOG_HLLC | HOG_HLL | HOG_RUSANOV | HOG_HLLEM | HOG_HLLI */
     int bc[3];           /* per axis HOG_PERIODIC | HOG_OUTFLOW | HOG_EXTERNAL (last axis) */
     int precision;       /* HOG_FP64 | HOG_MIXED */
     int linear_weno;     /* 1: WENO nonlinear weights replaced by the linear ones */

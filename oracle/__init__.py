@@ -43,7 +43,7 @@ class OCfg(C.Structure):
         ("gamma", C.c_double), ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
         ("cfl", C.c_double), ("weno_eps", C.c_double),
         ("g3", C.c_double * 3), ("g4", C.c_double * 4),
-        ("stepper", C.c_int),
+        ("stepper", C.c_int), ("char_recon", C.c_int),
     ]
 
 
@@ -101,6 +101,7 @@ def lib():
         L.oracle_rk_table.restype = C.c_int
         L.oracle_rk_operator.argtypes = [cp, dp, C.c_double, dp]
         L.oracle_rk_operator.restype = C.c_int
+        L.oracle_char_eigen.argtypes = [cp, C.c_int, dp, dp, dp]
         L.oracle_mc.argtypes = [C.c_double, C.c_double, C.c_double]
         L.oracle_mc.restype = C.c_double
         _lib = L
@@ -108,7 +109,8 @@ def lib():
 
 
 def make_cfg(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("periodic",) * 3,
-             linear_weno=False, eps=DEFAULT_EPS, g3=DEFAULT_G3, g4=DEFAULT_G4, positivity=True, stepper="ader"):
+             linear_weno=False, eps=DEFAULT_EPS, g3=DEFAULT_G3, g4=DEFAULT_G4, positivity=True, stepper="ader",
+             characteristic=False):
     c = OCfg()
     c.ndim = ndim
     c.nx, c.ny, c.nz = int(n[0]), int(n[1]), int(n[2]) if ndim == 3 else 1
@@ -128,6 +130,7 @@ def make_cfg(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("periodi
     for i in range(4):
         c.g4[i] = g4[i]
     c.stepper = STEPPER[stepper] if isinstance(stepper, str) else int(stepper)
+    c.char_recon = int(bool(characteristic))
     return c
 
 
@@ -330,3 +333,14 @@ def dleg(a, ap):
 
 def tint(e, ep):
     return lib().oracle_tint(e, ep)
+
+
+def char_eigen(cfg, d, U):
+    """Right eigenvectors (columns of R) of the flux Jacobian along axis d at
+    the conserved state U, and L = R^-1, as used by the characteristic
+    reconstruction."""
+    nv = cfg.ndim + 2
+    R = np.zeros((nv, nv))
+    L = np.zeros((nv, nv))
+    lib().oracle_char_eigen(C.byref(cfg), d, _state(U), R, L)
+    return R, L

@@ -65,6 +65,7 @@ typedef struct {
     double g3[3];      /* O3 linear weights for the L, C, R quadratics */
     double g4[4];      /* O4 linear weights for the H (cubic), L, C, R members */
     int stepper;       /* 0 ADER (the predictor / Hancock step); 2, 3, 4: SSP-RK with 2, 3, 5 stages */
+    int char_recon;    /* 1: WENO on characteristic variables (orders 3 and 4) */
 } ocfg;
 
 /* ------------------------------------------------------------------------ */
@@ -257,7 +258,7 @@ void oracle_riemann(const ocfg *c, int dir, const double *UL, const double *UR, 
          *   HLLEM: ct / (ct + |ut_n|)                (1 for a resting contact),
          *   HLLI:  1 - min(ut_n, 0)/SL - max(ut_n, 0)/SR
          * (an isolated contact moving at ut_n is then resolved exactly). */
-        double ut[3], dU[MAXV];
+        double ut[3] = {0.0, 0.0, 0.0}, dU[MAXV] = {0.0};
         for (int d = 0; d < nd; ++d) ut[d] = (sL * UL[1 + d] / rL + sR * UR[1 + d] / rR) / (sL + sR);
         for (int v = 0; v < nv; ++v) dU[v] = UR[v] - UL[v];
         double udm = 0.0;
@@ -395,9 +396,13 @@ void oracle_weno1d(const ocfg *cf, int p, const double *v5, double *out)
  * [dz][dy] (2D: [dy]); an application centred at a flagged zone uses the
  * linear weights.  maxdev (may be NULL): max_k |omega_k/gamma_k - 1| over all
  * variables and all applications centred at the zone itself. */
+static void recon_block_char(const ocfg *cf, const double *blk, double *W, const unsigned char *fl,
+                             double *maxdev);
+
 void oracle_recon_block_ex(const ocfg *cf, const double *blk, double *W, const unsigned char *fl,
                            double *maxdev)
 {
+    if (cf->char_recon) { recon_block_char(cf, blk, W, fl, maxdev); return; }
     int nd = cf->ndim, nv = nd + 2, p = cf->order - 1;
     mode4 m[MAXST];
     int nst = st_modes(nd, p, m);
@@ -456,6 +461,185 @@ void oracle_recon_block_ex(const ocfg *cf, const double *blk, double *W, const u
             W[k * nv + v] = val;
         }
     }
+#undef FLAG
+    if (maxdev) *maxdev = dmax;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Characteristic-variable reconstruction (the alternative to the            */
+/* component-wise reconstruction on conserved variables, Sec. I.1)           */
+/* ------------------------------------------------------------------------ */
+/* Right eigenvectors of the Jacobian of the flux along axis dir at the
+ * conserved state U, as the columns of R: the u_n - c acoustic wave, the
+ * entropy wave, one shear wave per tangential axis (in increasing axis order)
+ * and the u_n + c acoustic wave. */
+static void char_right(const ocfg *c, int dir, const double *U, double R[MAXV][MAXV])
+{
+    int nd = c->ndim, nv = nd + 2;
+    double rho = U[0], u[3] = {0.0, 0.0, 0.0}, q2 = 0.0;
+    for (int d = 0; d < nd; ++d) { u[d] = U[1 + d] / rho; q2 += u[d] * u[d]; }
+    double p = pressure(c, U);
+    double a = sqrt(c->gamma * p / rho);
+    double H = (U[nv - 1] + p) / rho;
+    memset(R, 0, sizeof(double) * MAXV * MAXV);
+    R[0][0] = 1.0;
+    R[0][1] = 1.0;
+    R[0][nv - 1] = 1.0;
+    for (int d = 0; d < nd; ++d) {
+        R[1 + d][0] = u[d] - (d == dir ? a : 0.0);
+        R[1 + d][1] = u[d];
+        R[1 + d][nv - 1] = u[d] + (d == dir ? a : 0.0);
+    }
+    R[nv - 1][0] = H - u[dir] * a;
+    R[nv - 1][1] = 0.5 * q2;
+    R[nv - 1][nv - 1] = H + u[dir] * a;
+    int col = 2;
+    for (int d = 0; d < nd; ++d) {
+        if (d == dir) continue;
+        R[1 + d][col] = 1.0;
+        R[nv - 1][col] = u[d];
+        ++col;
+    }
+}
+
+/* Inverse of the n x n matrix A by Gauss-Jordan elimination with partial
+ * pivoting. */
+static void invert(int n, double A[MAXV][MAXV], double X[MAXV][MAXV])
+{
+    double M[MAXV][2 * MAXV];
+    for (int r = 0; r < n; ++r)
+        for (int q = 0; q < n; ++q) { M[r][q] = A[r][q]; M[r][n + q] = (r == q) ? 1.0 : 0.0; }
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+        if (piv != col)
+            for (int q = 0; q < 2 * n; ++q) { double t = M[col][q]; M[col][q] = M[piv][q]; M[piv][q] = t; }
+        double inv = 1.0 / M[col][col];
+        for (int q = 0; q < 2 * n; ++q) M[col][q] *= inv;
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            double f = M[r][col];
+            for (int q = 0; q < 2 * n; ++q) M[r][q] -= f * M[col][q];
+        }
+    }
+    for (int r = 0; r < n; ++r)
+        for (int q = 0; q < n; ++q) X[r][q] = M[r][n + q];
+}
+
+void oracle_char_eigen(const ocfg *c, int dir, const double *U, double *R, double *L)
+{
+    double Rm[MAXV][MAXV], Lm[MAXV][MAXV];
+    int nv = c->ndim + 2;
+    char_right(c, dir, U, Rm);
+    invert(nv, Rm, Lm);
+    for (int r = 0; r < nv; ++r)
+        for (int q = 0; q < nv; ++q) { R[r * nv + q] = Rm[r][q]; L[r * nv + q] = Lm[r][q]; }
+}
+
+/* One 1D application on characteristic variables: lines[v][0..4] of all
+ * variables along axis dir, ref the conserved state that defines the fields
+ * (the mean of the zone the application is centred at).  Projects each
+ * point on the fields (w = L u), applies the WENO operator to each field and
+ * maps the coefficients back (c = R c_w).  out[v][1..p]; *dev receives the
+ * largest weight deviation over the fields. */
+static void weno_char(const ocfg *cf, int p, int dir, const double *ref, double lines[MAXV][5], int linear,
+                      double out[MAXV][4], double *dev)
+{
+    int nv = cf->ndim + 2;
+    double R[MAXV][MAXV], L[MAXV][MAXV];
+    char_right(cf, dir, ref, R);
+    invert(nv, R, L);
+    double cw[MAXV][4];
+    double dmax = 0.0;
+    for (int k = 0; k < nv; ++k) {
+        double w[5];
+        for (int o = 0; o < 5; ++o) {
+            w[o] = 0.0;
+            for (int v = 0; v < nv; ++v) w[o] += L[k][v] * lines[v][o];
+        }
+        double dv = 0.0;
+        weno1d_core(cf, p, w, linear, cw[k], &dv);
+        dmax = fmax(dmax, dv);
+    }
+    for (int v = 0; v < nv; ++v)
+        for (int a = 0; a <= p; ++a) {
+            out[v][a] = 0.0;
+            if (a == 0) continue;
+            for (int k = 0; k < nv; ++k) out[v][a] += R[v][k] * cw[k][a];
+        }
+    if (dev) *dev = dmax;
+}
+
+/* The successive x -> y -> z sweeps of oracle_recon_block_ex with every 1D
+ * application done on characteristic variables (weno_char): the x
+ * application on the line through (dz, dy) takes the fields of that line's
+ * centre zone, the y application of plane dz those of zone (0, 0, dz), the
+ * z application those of the zone itself. */
+static void recon_block_char(const ocfg *cf, const double *blk, double *W, const unsigned char *fl, double *maxdev)
+{
+    int nd = cf->ndim, nv = nd + 2, p = cf->order - 1;
+    mode4 m[MAXST];
+    int nst = st_modes(nd, p, m);
+    int nzb = (nd == 3) ? 5 : 1;
+    int zc = (nd == 3) ? 2 : 0;
+    double dmax = 0.0;
+#define BLK(v, z, y, x) blk[(((v) * nzb + (z)) * 5 + (y)) * 5 + (x)]
+#define FLAG(z, y) (cf->linear_weno || (fl && fl[(z) * 5 + (y)]))
+    double A[MAXP + 1][5][5][MAXV];
+    for (int z = 0; z < nzb; ++z)
+        for (int y = 0; y < 5; ++y) {
+            double lines[MAXV][5], ref[MAXV], c[MAXV][4], dv = 0.0;
+            for (int v = 0; v < nv; ++v) {
+                for (int x = 0; x < 5; ++x) lines[v][x] = BLK(v, z, y, x);
+                ref[v] = BLK(v, z, y, 2);
+            }
+            weno_char(cf, p, 0, ref, lines, FLAG(z, y), c, &dv);
+            if (z == zc && y == 2) dmax = fmax(dmax, dv);
+            for (int v = 0; v < nv; ++v) {
+                A[0][z][y][v] = lines[v][2];
+                for (int a = 1; a <= p; ++a) A[a][z][y][v] = c[v][a];
+            }
+        }
+    double B[MAXP + 1][MAXP + 1][5][MAXV];
+    for (int z = 0; z < nzb; ++z) {
+        double ref[MAXV];
+        for (int v = 0; v < nv; ++v) ref[v] = BLK(v, z, 2, 2);
+        for (int a = 0; a <= p; ++a) {
+            double lines[MAXV][5], c[MAXV][4], dv = 0.0;
+            for (int v = 0; v < nv; ++v) {
+                for (int y = 0; y < 5; ++y) lines[v][y] = A[a][z][y][v];
+                B[a][0][z][v] = lines[v][2];
+            }
+            if (p - a < 1) continue;
+            weno_char(cf, p, 1, ref, lines, FLAG(z, 2), c, &dv);
+            if (z == zc) dmax = fmax(dmax, dv);
+            for (int v = 0; v < nv; ++v)
+                for (int bb = 1; bb <= p - a; ++bb) B[a][bb][z][v] = c[v][bb];
+        }
+    }
+    double C[MAXP + 1][MAXP + 1][MAXP + 1][MAXV];
+    for (int a = 0; a <= p; ++a)
+        for (int bb = 0; a + bb <= p; ++bb) {
+            for (int v = 0; v < nv; ++v) C[a][bb][0][v] = B[a][bb][zc][v];
+            if (nd == 2 || p - a - bb < 1) continue;
+            double lines[MAXV][5], ref[MAXV], c[MAXV][4], dv = 0.0;
+            for (int v = 0; v < nv; ++v) {
+                for (int z = 0; z < 5; ++z) lines[v][z] = B[a][bb][z][v];
+                ref[v] = BLK(v, 2, 2, 2);
+            }
+            weno_char(cf, p, 2, ref, lines, FLAG(2, 2), c, &dv);
+            dmax = fmax(dmax, dv);
+            for (int v = 0; v < nv; ++v)
+                for (int cc = 1; cc <= p - a - bb; ++cc) C[a][bb][cc][v] = c[v][cc];
+        }
+    int k = 0;
+    for (int i = 0; i < nst; ++i) {
+        if (m[i].e != 0) continue;
+        for (int v = 0; v < nv; ++v) W[k * nv + v] = C[m[i].a][m[i].b][m[i].c][v];
+        ++k;
+    }
+#undef BLK
 #undef FLAG
     if (maxdev) *maxdev = dmax;
 }

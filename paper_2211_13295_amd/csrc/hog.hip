@@ -69,7 +69,7 @@ int check_cfg(const hog_config* c)
         return fail(HOG_EINVAL, "the second-order scheme runs on the FP64 path only");
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return fail(HOG_EINVAL, "zone counts must be >= 1");
     if (c->ndim == 2 && c->nz != 1) return fail(HOG_EINVAL, "nz must be 1 in 2D");
-    if (c->riemann < 0 || c->riemann > 2) return fail(HOG_EINVAL, "unknown Riemann solver %d", c->riemann);
+    if (c->riemann < 0 || c->riemann > 4) return fail(HOG_EINVAL, "unknown Riemann solver %d", c->riemann);
     for (int d = 0; d < 3; ++d)
         if (c->bc[d] != HOG_PERIODIC && c->bc[d] != HOG_OUTFLOW && c->bc[d] != HOG_EXTERNAL)
             return fail(HOG_EINVAL, "bad boundary type on axis %d", d);
@@ -366,6 +366,10 @@ int enqueue_o2(hog_grid* g, double dt_user)
             taps ? launch(k_o2_step<D, HOG_HLLC, true, false>) : launch(k_o2_step<D, HOG_HLLC, false, false>);
         else if (g->cfg.riemann == HOG_HLL)
             taps ? launch(k_o2_step<D, HOG_HLL, true, false>) : launch(k_o2_step<D, HOG_HLL, false, false>);
+        else if (g->cfg.riemann == HOG_HLLEM)
+            taps ? launch(k_o2_step<D, HOG_HLLEM, true, false>) : launch(k_o2_step<D, HOG_HLLEM, false, false>);
+        else if (g->cfg.riemann == HOG_HLLI)
+            taps ? launch(k_o2_step<D, HOG_HLLI, true, false>) : launch(k_o2_step<D, HOG_HLLI, false, false>);
         else taps ? launch(k_o2_step<D, HOG_RUSANOV, true, false>) : launch(k_o2_step<D, HOG_RUSANOV, false, false>);
     }
     return launch_check("second-order step");
@@ -407,6 +411,8 @@ int enqueue_rk(hog_grid* g, double dt_user)
             };
             if (g->cfg.riemann == HOG_HLLC) launch(k_o2_step<D, HOG_HLLC, false, true>);
             else if (g->cfg.riemann == HOG_HLL) launch(k_o2_step<D, HOG_HLL, false, true>);
+            else if (g->cfg.riemann == HOG_HLLEM) launch(k_o2_step<D, HOG_HLLEM, false, true>);
+            else if (g->cfg.riemann == HOG_HLLI) launch(k_o2_step<D, HOG_HLLI, false, true>);
             else launch(k_o2_step<D, HOG_RUSANOV, false, true>);
         } else {
             double* A = static_cast<double*>(g->A);

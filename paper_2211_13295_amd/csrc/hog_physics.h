@@ -100,10 +100,19 @@ __device__ __forceinline__ void flux_dir(const T* U, T gm1, int dir, T* F, T& p,
     F[D + 1] = (U[D + 1] + p) * un;
 }
 
-// Riemann solvers at a face with normal axis dir.  solver: 0 HLLC, 1 HLL, 2 Rusanov.
+// Riemann solvers at a face with normal axis dir.  solver: 0 HLLC, 1 HLL,
+// 2 Rusanov, 3 HLLEM, 4 HLLI (the solvers Sec. I.1 favours for their small
+// operation count and cache use; Fig. 5 builds HLL/HLLEM fluxes).
 // HLLC follows Toro, Spruce and Speares with Einfeldt wave-speed bounds built
 // from Roe averages; branch ties resolved as S_L >= 0 -> left, S* >= 0 -> left
 // star, S_R > 0 -> right star, else right.
+// HLLEM (Einfeldt) and HLLI (Dumbser and Balsara) take the HLL flux and remove
+// the part of its dissipation that falls on the linearly degenerate waves of
+// Roe's linearisation: the entropy wave of strength drho - dp / c~^2 along
+// (1, u~, |u~|^2 / 2) and one shear wave per tangential axis t of strength
+// rho~ du_t (rho~ = sqrt(rho_L rho_R)) along (0, e_t, u~_t), scaled by
+// delta = c~ / (c~ + |u~_n|) (HLLEM) or 1 - min(u~_n, 0)/S_L - max(u~_n, 0)/S_R
+// (HLLI, which makes an isolated moving contact exact).
 // RCP: divisions as products with Newton-refined reciprocals (see dv).
 template <int D, typename T = double, bool RCP = false>
 __device__ __forceinline__ void riemann(const T* UL, const T* UR, int dir, int solver, T gamma, T* F)
@@ -124,18 +133,18 @@ __device__ __forceinline__ void riemann(const T* UL, const T* UR, int dir, int s
     const T sL = sqrt(rL), sR = sqrt(rR);
     const T isum = dv<RCP>(T(1), sL + sR);
     const T HL = dv<RCP>(UL[NV - 1] + pL, rL), HR = dv<RCP>(UR[NV - 1] + pR, rR);
-    T q2 = T(0), utn = T(0);
+    T q2 = T(0), utn = T(0), ut[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const T ut = (dv<RCP>(UL[1 + d], sL) + dv<RCP>(UR[1 + d], sR)) * isum;
-        q2 += ut * ut;
-        if (d == dir) utn = ut;
+        ut[d] = (dv<RCP>(UL[1 + d], sL) + dv<RCP>(UR[1 + d], sR)) * isum;
+        q2 += ut[d] * ut[d];
+        if (d == dir) utn = ut[d];
     }
     const T Ht = (sL * HL + sR * HR) * isum;
     const T ct = sqrt(gm1 * (Ht - T(0.5) * q2));
     const T SL = fmin(uL - cL, utn - ct);
     const T SR = fmax(uR + cR, utn + ct);
-    if (solver == 1) {
+    if (solver == 1 || solver >= 3) {
         if (SL >= T(0)) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] = FL[v];
@@ -146,6 +155,29 @@ __device__ __forceinline__ void riemann(const T* UL, const T* UR, int dir, int s
             const T id = dv<RCP>(T(1), SR - SL);
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (UR[v] - UL[v])) * id;
+            if (solver >= 3) {
+                // degenerate-wave content of the jump, from primitive jumps
+                const T ae = (rR - rL) - dv<RCP>(pR - pL, ct * ct);
+                const T rt = sL * sR;
+                const T irL = dv<RCP>(T(1), rL), irR = dv<RCP>(T(1), rR);
+                T J[NV];
+                J[0] = ae;
+                J[NV - 1] = T(0.5) * ae * q2;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    J[1 + d] = ae * ut[d];
+                    if (d != dir) {
+                        const T at = rt * (UR[1 + d] * irR - UL[1 + d] * irL);
+                        J[1 + d] += at;
+                        J[NV - 1] += at * ut[d];
+                    }
+                }
+                const T delta = (solver == 3) ? dv<RCP>(ct, ct + fabs(utn))
+                                              : T(1) - dv<RCP>(fmin(utn, T(0)), SL) - dv<RCP>(fmax(utn, T(0)), SR);
+                const T k = SL * SR * id * delta;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) F[v] -= k * J[v];
+            }
         }
         return;
     }

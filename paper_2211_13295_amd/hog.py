@@ -19,7 +19,7 @@ HOG_OK, HOG_EINVAL, HOG_ENOMEM, HOG_EDEVICE, HOG_ENONPHYS, HOG_ESTATE = 0, -1, -
 SOA, AOS = 0, 1
 HOST, DEVICE = 0, 1
 TAP_MODES, TAP_STMODES, TAP_FLUX_X, TAP_FLUX_Y, TAP_FLUX_Z = 1, 2, 3, 4, 5
-RIEMANN = {"hllc": 0, "hll": 1, "rusanov": 2}
+RIEMANN = {"hllc": 0, "hll": 1, "rusanov": 2, "hllem": 3, "hlli": 4}
 BC = {"periodic": 0, "outflow": 1, "external": 2}
 PRECISION = {"fp64": 0, "mixed": 1}
 STEPPER = {"ader": 0, "rk2": 2, "rk3": 3, "rk4": 4}

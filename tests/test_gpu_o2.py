@@ -49,7 +49,7 @@ SIZES_3D = [(37, 30, 21), (28, 14, 16), (15, 29, 9)]
 SIZES_2D = [(600, 45, 1), (254, 17, 1), (255, 8, 1)]
 
 
-@pytest.mark.parametrize("riemann", ["hllc", "hll", "rusanov"])
+@pytest.mark.parametrize("riemann", ["hllc", "hll", "rusanov", "hllem", "hlli"])
 @pytest.mark.parametrize("bc", ["periodic", "outflow"])
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_o2_one_step_matches_oracle(hog, ndim, bc, riemann):

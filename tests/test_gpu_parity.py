@@ -90,7 +90,7 @@ def test_stage_modes_match_oracle(hog, ndim, order):
 
 # ---------------------------------------------------------------- one step
 @pytest.mark.parametrize("ndim,order", CASES)
-@pytest.mark.parametrize("riemann", ["hllc", "hll", "rusanov"])
+@pytest.mark.parametrize("riemann", ["hllc", "hll", "rusanov", "hllem", "hlli"])
 @pytest.mark.parametrize("bc", ["periodic", "outflow"])
 def test_one_step_matches_oracle(hog, ndim, order, riemann, bc):
     note(f"one step ndim={ndim} order={order} riemann={riemann} bc={bc}")
@@ -188,13 +188,14 @@ def test_vortex3d_perturbed_reduced_matches_oracle(hog):
     assert rel_l1(U, Uo) <= REL_L1
 
 
-def test_sod_run_matches_oracle(hog):
-    note("sod 3D along z O4")
+@pytest.mark.parametrize("riemann", ["hllc", "hllem", "hlli"])
+def test_sod_run_matches_oracle(hog, riemann):
+    note(f"sod 3D along z O4 {riemann}")
     pb = icgen.sod(n=64, axis=2, ndim=3, ntrans=3)
-    g = grid_for(hog, pb, 4)
+    g = grid_for(hog, pb, 4, riemann=riemann)
     t = g.advance(1000, t_end=0.05)
     U = g.get_state()
-    c = oracle.cfg_from_problem(pb, 4)
+    c = oracle.cfg_from_problem(pb, 4, riemann=riemann)
     Uo, to, _ = oracle.run(c, pb.U, t_end=0.05)
     assert abs(t - to) <= 1e-12
     assert rel_l1(U, Uo) <= REL_L1

@@ -53,7 +53,7 @@ def test_rk_one_step_matches_oracle(hog, ndim, bc, order, stepper):
 
 
 @pytest.mark.parametrize("stepper", ["rk2", "rk4"])
-@pytest.mark.parametrize("riemann", ["hll", "rusanov"])
+@pytest.mark.parametrize("riemann", ["hll", "rusanov", "hllem", "hlli"])
 def test_rk_other_pairings_and_solvers(hog, stepper, riemann):
     """Steppers are independent of the order: third order with two and five
     stages, HLL and Rusanov."""
