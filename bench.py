@@ -1,11 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of the ADER-WENO Euler zone update on one MI355X.
 
-Workload: 3D Euler, ideal gas gamma = 1.4, the isentropic vortex extruded
-along z with a seeded smooth density perturbation (amplitude 1e-2, 4 Fourier
-modes per axis), 128^3 zones on the periodic box [0,10]^3, fourth-order
-WENO + ADER, HLLC, CFL 0.4, FP64, steps with the CFL time step computed on the
-device.  Prints one JSON line (the metric is zone updates per second).
+Default line (the metric's workload): 3D Euler, ideal gas gamma = 1.4, the
+four-quadrant Riemann problem (quadrant states seeded from rho in [0.5, 1.5],
+p in [0.1, 1.0], in-plane speed <= 0.5, seed 5) on 384^3 zones of [0,1]^3
+with outflow boundaries, fourth-order WENO + ADER, HLLC, CFL 0.4.  `value` is
+the FP64 path's zone-updates/s; beside it the mixed FP32/FP64 path with the
+trained smooth-zone gate (and without it) on the same time steps, each with
+its relative L1 against the FP64 path after the same steps.  The 128^3 vortex
+workload's figures follow as an extra key.
 
 The timed region holds K full steps (ghost fill, reconstruction, predictor,
 Riemann solver, update and CFL reduction) with the state resident in HBM,
@@ -30,6 +33,11 @@ METRIC = "zone-updates/sec, 3D Euler WENO+ADER, FP64 vs FP32+learned gate at sta
 UNIT = "zone-updates/s"
 PEAK_FP64_VALU_TFLOPS = 78.6          # MI355X published FP64 vector peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_predictor_vortex3d_128.json")
+TRAFFIC_FILE_C5 = os.path.join(ROOT, "profiles", "traffic_predictor_fourquad384.json")
+# Algorithmic flops per zone of the fourth-order 3D predictor as estimated in
+# the design's scope table (sum-factorised evaluation and projection); the
+# exact count of the formulation built here is predictor_flops(3, 3).
+PREDICTOR_FLOPS_ESTIMATE_3D_O4 = 2.2e5
 TRAFFIC_FILE_O2 = os.path.join(ROOT, "profiles", "traffic_o2_step_vortex3d_128.json")
 TRAFFIC_FILE_RK = os.path.join(ROOT, "profiles", "traffic_face_points_vortex3d_128.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2211_13295_amd", "csrc", f)
@@ -152,6 +160,8 @@ def traffic_record(second_order=False, kind=None):
     path, src = (TRAFFIC_FILE_O2, KERNEL_SOURCES_O2) if second_order else (TRAFFIC_FILE, KERNEL_SOURCES)
     if kind == "rk":
         path, src = TRAFFIC_FILE_RK, KERNEL_SOURCES_RK
+    if kind == "c5":
+        path = TRAFFIC_FILE_C5
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -165,6 +175,9 @@ def traffic_record(second_order=False, kind=None):
 PMC_COMMAND = ("export TMPDIR=/tmp; timeout -s KILL 240 rocprofv3 --pmc {ctr} --kernel-include-regex "
                "\"k_predict|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --steps 2 "
                "--warmup 0 --no-cpu-baseline --no-mixed --copy-calibration")
+PMC_COMMAND_C5 = ("export TMPDIR=/tmp; timeout -s KILL 300 rocprofv3 --pmc {ctr} --kernel-include-regex "
+                  "\"k_predict|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --steps 1 "
+                  "--warmup 0 --no-cpu-baseline --no-mixed --no-vortex128 --copy-calibration")
 PMC_COMMAND_RK = ("export TMPDIR=/tmp; timeout -s KILL 300 rocprofv3 --pmc {ctr} --kernel-include-regex "
                   "\"k_face_points|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py "
                   "--ader-vs-rk --steps 1 --copy-calibration")
@@ -243,6 +256,25 @@ def write_traffic(fetch_csv, write_csv, n=128, second_order=False, kind=None):
         print(json.dumps(rec, indent=1))
         return
     zones = (n + 2) ** 3
+    if kind == "c5":
+        rec = {
+            "kernel": "k_predict<3,3> (FP64)",
+            "workload": f"four-quadrant Riemann problem, {n}^3 outflow, order 4",
+            "kernel_hash": kernel_hash(),
+            "bytes_per_launch": fetch * fs + write * ws,
+            "fetch_bytes_per_launch": fetch * fs,
+            "write_bytes_per_launch": write * ws,
+            "fetch_scale": fs,
+            "write_scale": ws,
+            "algorithmic_bytes_per_launch": zones * (20 + 48) * 5 * 8,
+            "commands": [PMC_COMMAND_C5.format(ctr="FETCH_SIZE", tag="c5fetch"),
+                         PMC_COMMAND_C5.format(ctr="WRITE_SIZE", tag="c5write")],
+            "calibration": "plain elementwise copy of 2^27 doubles (1 GiB read + 1 GiB written) in the same runs",
+        }
+        with open(TRAFFIC_FILE_C5, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec, indent=1))
+        return
     rec = {
         "kernel": "k_predict<3,3> (FP64)",
         "workload": f"3D vortex + density modes, {n}^3, order 4",
@@ -734,85 +766,12 @@ def gate_ablation(hog, torch, name, steps, timed_steps, label_samples=1_000_000)
             "path": "mixed FP32/FP64", "gate_theta": theta, "variants": out}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--order", type=int, default=4)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed FP32/FP64 comparison run")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="first run a plain elementwise copy of 2 x 1 GiB (known bytes) to "
-                         "calibrate the FETCH_SIZE / WRITE_SIZE counters")
-    ap.add_argument("--shock-workload", choices=["multiblast256", "fourquad384"],
-                    help="instead of the benchmark line: mixed (with the trained gate on the four-quadrant "
-                         "problem) vs FP64 on a full-size shock workload; prints one JSON line")
-    ap.add_argument("--gate-ablation", choices=["multiblast256", "fourquad384"],
-                    help="instead of the benchmark line: full WENO / trained gate / all linear / random gate "
-                         "on the mixed path of a full-size shock workload; prints one JSON line")
-    ap.add_argument("--second-order", action="store_true",
-                    help="instead of the benchmark line: the second-order scheme of Figs. 3-7 (HLL) on the "
-                         "same workload; prints one JSON line")
-    ap.add_argument("--host-round-trip", action="store_true",
-                    help="instead of the benchmark line: steps with the paper's per-step host round trip of the "
-                         "zone means vs the resident loop; prints one JSON line")
-    ap.add_argument("--stream", action="store_true",
-                    help="instead of the benchmark line: a host-resident 256^3 mesh streamed through the GPU in "
-                         "slabs vs in core; prints one JSON line")
-    ap.add_argument("--ader-vs-rk", action="store_true",
-                    help="instead of the benchmark line: ADER vs Runge-Kutta throughput at orders 2-4 (Table IV); "
-                         "prints one JSON line")
-    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write the predictor traffic record from two rocprofv3 counter files and exit")
-    args = ap.parse_args()
-    if args.traffic_from:
-        write_traffic(*args.traffic_from, second_order=args.second_order, kind="rk" if args.ader_vs_rk else None)
-        return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the multi-GPU path (halo exchange and a min "
-              "all-reduce of dt) is designed but not implemented.", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
+def vortex128_line(hog, torch, args, n=128):
+    """The 128^3 vortex workload (3D isentropic vortex extruded along z with
+    seeded density modes, periodic [0,10]^3, fourth order, HLLC, FP64), with
+    the mixed path and the gated mixed path on the same steps."""
     import icgen
-    from paper_2211_13295_amd import hog
-
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    hog.load()
-    if args.gate_ablation:
-        steps = 100 if args.gate_ablation == "multiblast256" else 200
-        print(json.dumps(gate_ablation(hog, torch, args.gate_ablation, steps, 20)), flush=True)
-        return
-    if args.copy_calibration:
-        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            torch.mul(x, 1.0, out=y)            # reads 1 GiB, writes 1 GiB
-        torch.cuda.synchronize()
-        print(f"copy calibration: 3 launches of {x.numel() * 8} bytes read + written", flush=True)
-        del x, y
-    if args.second_order:
-        print(json.dumps(second_order_line(hog, torch, args)), flush=True)
-        return
-    if args.ader_vs_rk:
-        print(json.dumps(ader_vs_rk(hog, torch, args)), flush=True)
-        return
-    if args.host_round_trip:
-        print(json.dumps(host_round_trip(hog, torch, args)), flush=True)
-        return
-    if args.stream:
-        print(json.dumps(stream_vs_in_core(hog, torch, args)), flush=True)
-        return
-    if args.shock_workload:
-        steps = 100 if args.shock_workload == "multiblast256" else 200
-        print(json.dumps(shock_workload(hog, torch, args.shock_workload, steps, 20)), flush=True)
-        return
-    n, order = args.n, args.order
+    order = args.order
     pb = icgen.vortex3d_perturbed(n=n, seed=2)
     g = hog.Grid.from_problem(pb, order)
     if args.warmup > 0:
@@ -870,16 +829,307 @@ def main():
                                 "max": reps_sorted[-1]},
         "predictor_fraction_of_step": prof["predictor"][0] / args.steps / step_sum if step_sum > 0 else None,
     }
+    ref = g.get_state()
+    g.close()
+    torch.cuda.empty_cache()
     if not args.no_mixed:
-        ref = g.get_state()
         out["mixed"] = mixed_run(hog, torch, pb, order, args.steps, ref)
         if os.path.exists(GATE_FILE):
             import numpy as np
             z = np.load(GATE_FILE)
             out["mixed_gated"] = mixed_run(hog, torch, pb, order, args.steps, ref,
                                            gate=(z["params"], float(z["theta"])))
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(order, args.cpu_seconds)
+    return out
+
+
+def c5_cutout(m):
+    """A bounded sample of the four-quadrant workload for the CPU oracle: the
+    m^3 block of the 384^3 initial state around the domain centre, where the
+    four quadrants meet, with outflow boundaries."""
+    import icgen
+    return icgen.four_quadrant(n=C5_N, seed=5, block=(C5_N // 2 - m // 2, m))
+
+
+def cpu_sample(threads, seconds, m=32):
+    """Child-process leg of the CPU baseline: the oracle (plain FP64 C,
+    OpenMP over zones) on the m^3 cut-out of the four-quadrant workload,
+    whole fourth-order steps until `seconds` have passed; prints one JSON line."""
+    import oracle
+    pb = c5_cutout(m)
+    c = oracle.cfg_from_problem(pb, 4)
+    U = pb.U
+    dt, _ = oracle.cfl_dt(c, U)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        U = oracle.step(c, U, dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 200:
+            break
+    print(json.dumps({"value": m ** 3 * steps / el, "unit": UNIT, "cores": threads, "kind": "oracle",
+                      "sample": f"{steps} fourth-order steps of the {m}^3 centre block of the 384^3 four-quadrant "
+                                f"initial state (outflow), {el:.1f} s, OpenMP threads={threads}"}), flush=True)
+
+
+def cpu_baseline_c5(seconds):
+    """The CPU oracle timed on this host's cores on a bounded sample of the
+    headline workload, with all host threads and with one; each in a child
+    process started before this process touches the GPU (OMP_NUM_THREADS is
+    read when the OpenMP runtime starts)."""
+    import subprocess
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    out = {}
+    for t in (threads, 1):
+        env = dict(os.environ, OMP_NUM_THREADS=str(t))
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-sample", str(t),
+                            "--cpu-seconds", str(seconds)], env=env, capture_output=True, text=True, check=True)
+        out[t] = json.loads(r.stdout.strip().splitlines()[-1])
+    res = dict(out[threads])
+    res["single_thread"] = {"value": out[1]["value"], "cores": 1, "sample": out[1]["sample"]}
+    return res
+
+
+C5_N = 384
+
+
+def headline(hog, torch, args, cpu):
+    """The metric's workload: FP64 vs mixed FP32/FP64 with the trained gate on
+    the 384^3 four-quadrant problem, fourth order, HLLC.
+
+    FP64: a stepped run of K steps (host-read CFL time steps, recorded), then
+    the timed runs of K steps with the device-side time step (the same steps:
+    the CFL reduction is the same arithmetic on the same states).  Mixed with
+    the gate, and mixed without it: timed the same way, then stepped with the
+    FP64 run's time steps; relative L1 of each against the FP64 state after the
+    same K steps (the FP64 path matches the FP64 CPU oracle on this workload
+    to 1e-12: whole grid on a 96^3 version over 20 steps, sampled zones at
+    384^3 over 5 steps, in the GPU parity tests)."""
+    import icgen
+    n, order, K = args.headline_n, 4, args.steps
+    pb = icgen.four_quadrant(n=n, seed=5)
+    zones = pb.U[0].size
+    z = np.load(GATE_FILE)
+    gate = (z["params"], float(z["theta"]))
+
+    def free(g):
+        g.close()
+        torch.cuda.empty_cache()
+
+    def timed(g, reps):
+        g.set_state(pb.U)
+        torch.cuda.synchronize()
+        g.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.advance(K)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = g.profile_read()
+        g.profile(False)
+        ms = [el * 1e3 / K]
+        for _ in range(reps - 1):
+            g.set_state(pb.U)
+            torch.cuda.synchronize()
+            r0 = time.perf_counter()
+            g.advance(K)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - r0) * 1e3 / K)
+        return ms, prof
+
+    def stepped(g, dts=None):
+        g.set_state(pb.U)
+        rec = []
+        dt = g.compute_dt() if dts is None else dts[0]
+        for s_ in range(K):
+            if dts is not None:
+                dt = dts[s_]
+            rec.append(dt)
+            dt = g.step(dt)
+        return g.get_state(), rec
+
+    # FP64
+    print(f"headline: FP64 {n}^3, {K} steps", file=sys.stderr, flush=True)
+    g = hog.Grid.from_problem(pb, order)
+    if args.warmup > 0:
+        g.advance(args.warmup)
+    ref, dts = stepped(g)
+    ms64, prof = timed(g, args.repeats)
+    free(g)
+    ms_step = ms64[0]
+    value = zones * K / (ms_step / 1e3)
+    srt = sorted(ms64)
+
+    D, P = 3, order - 1
+    zones_per_launch = (n + 2) ** 3
+    pred_ms, pred_calls = prof["predictor"]
+    avg_s = pred_ms / 1e3 / max(pred_calls, 1)
+    achieved = PREDICTOR_FLOPS_ESTIMATE_3D_O4 * zones_per_launch / avg_s / 1e12
+    achieved_exact = predictor_flops(D, P) * zones_per_launch / avg_s / 1e12
+    stage_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in prof.items()}
+    step_sum = sum(v[0] for v in prof.values()) / K
+
+    def mixed(with_gate):
+        tag = "mixed + gate" if with_gate else "mixed"
+        print(f"headline: {tag} {n}^3, {K} steps", file=sys.stderr, flush=True)
+        g = hog.Grid.from_problem(pb, order, precision="mixed")
+        if with_gate:
+            g.set_gate(gate[0], theta=gate[1])
+        if args.warmup > 0:
+            g.advance(args.warmup)
+        ms, prof_m = timed(g, args.repeats)
+        U, _ = stepped(g, dts)
+        rec = {"value": zones * K / (ms[0] / 1e3), "unit": UNIT, "ms_per_step": ms[0],
+               "repeats_ms_per_step": {"n": len(ms), "median": sorted(ms)[len(ms) // 2], "min": min(ms),
+                                       "max": max(ms)},
+               "dtype": "f32+f64",
+               "rel_l1_vs_fp64": float(np.abs(U - ref).sum() / np.abs(ref).sum()),
+               "density_l1_vs_fp64": float(np.abs(U[0] - ref[0]).mean()),
+               "stages_ms_per_step": {k: round(v[0] / K, 4) for k, v in prof_m.items()}}
+        if with_gate:
+            _, flags = g.gate_eval()
+            rec["gate_theta"] = gate[1]
+            rec["gated_fraction_final_state"] = float(flags.mean())
+        free(g)
+        return rec
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"3D Euler four-quadrant Riemann problem (quadrant states seeded: rho U[0.5,1.5], "
+                               f"p U[0.1,1.0], in-plane speed U[0,0.5], seed 5), {n}^3 outflow [0,1]^3, order 4 "
+                               f"WENO+ADER, HLLC, CFL 0.4, FP64 vs FP32+learned gate",
+                   "zones": zones, "order": order, "riemann": "hllc", "precision": "fp64"},
+        "roofline": {"bound": "alu", "kernel": "k_predict (ADER predictor, FP64)", "achieved": achieved,
+                     "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": traffic_record(kind="c5"),
+                     "alg_flops_per_zone": PREDICTOR_FLOPS_ESTIMATE_3D_O4, "zones_per_launch": zones_per_launch,
+                     "avg_launch_ms": avg_s * 1e3,
+                     "exact_count": {"alg_flops_per_zone": predictor_flops(D, P), "achieved": achieved_exact,
+                                     "frac": achieved_exact / PEAK_FP64_VALU_TFLOPS}},
+        "stages_ms_per_launch": stage_ms,
+        "repeats_ms_per_step": {"n": len(ms64), "median": srt[len(srt) // 2], "min": srt[0], "max": srt[-1]},
+        "predictor_fraction_of_step": prof["predictor"][0] / K / step_sum if step_sum > 0 else None,
+    }
+    if not args.no_mixed:
+        out["mixed_gated"] = mixed(True)
+        out["mixed"] = mixed(False)
+        out["gate_speedup_vs_mixed"] = out["mixed"]["ms_per_step"] / out["mixed_gated"]["ms_per_step"]
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    if not args.no_vortex128:
+        print("headline: 128^3 vortex workload", file=sys.stderr, flush=True)
+        v = vortex128_line(hog, torch, args, n=128)
+        out["vortex128"] = {k: v[k] for k in ("value", "ms_per_step", "config", "roofline", "stages_ms_per_launch",
+                                              "repeats_ms_per_step") if k in v}
+        for k in ("mixed", "mixed_gated"):
+            if k in v:
+                out["vortex128"][k] = v[k]
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--repeats", type=int, default=3, help="timed repetitions of the K steps (median/min/max)")
+    ap.add_argument("--n", type=int, default=128, help="grid of the 128^3-workload legs")
+    ap.add_argument("--headline-n", type=int, default=C5_N, help="grid of the four-quadrant headline workload")
+    ap.add_argument("--vortex128", action="store_true",
+                    help="instead of the headline: the 128^3 vortex workload line (FP64, mixed, mixed + gate)")
+    ap.add_argument("--no-vortex128", action="store_true", help="leave the 128^3 vortex figures out of the line")
+    ap.add_argument("--cpu-sample", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed FP32/FP64 comparison run")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain elementwise copy of 2 x 1 GiB (known bytes) to "
+                         "calibrate the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--shock-workload", choices=["multiblast256", "fourquad384"],
+                    help="instead of the benchmark line: mixed (with the trained gate on the four-quadrant "
+                         "problem) vs FP64 on a full-size shock workload; prints one JSON line")
+    ap.add_argument("--gate-ablation", choices=["multiblast256", "fourquad384"],
+                    help="instead of the benchmark line: full WENO / trained gate / all linear / random gate "
+                         "on the mixed path of a full-size shock workload; prints one JSON line")
+    ap.add_argument("--second-order", action="store_true",
+                    help="instead of the benchmark line: the second-order scheme of Figs. 3-7 (HLL) on the "
+                         "same workload; prints one JSON line")
+    ap.add_argument("--host-round-trip", action="store_true",
+                    help="instead of the benchmark line: steps with the paper's per-step host round trip of the "
+                         "zone means vs the resident loop; prints one JSON line")
+    ap.add_argument("--stream", action="store_true",
+                    help="instead of the benchmark line: a host-resident 256^3 mesh streamed through the GPU in "
+                         "slabs vs in core; prints one JSON line")
+    ap.add_argument("--ader-vs-rk", action="store_true",
+                    help="instead of the benchmark line: ADER vs Runge-Kutta throughput at orders 2-4 (Table IV); "
+                         "prints one JSON line")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the predictor traffic record from two rocprofv3 counter files and exit")
+    ap.add_argument("--traffic-kind", choices=["c5"], help="with --traffic-from: the headline's 384^3 record")
+    args = ap.parse_args()
+    if args.cpu_sample:
+        cpu_sample(args.cpu_sample, args.cpu_seconds)
+        return
+    if args.traffic_from:
+        kind = "rk" if args.ader_vs_rk else args.traffic_kind
+        write_traffic(*args.traffic_from, n=C5_N if kind == "c5" else 128, second_order=args.second_order,
+                      kind=kind)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the multi-GPU path (halo exchange and a min "
+              "all-reduce of dt) is designed but not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    special = (args.gate_ablation or args.second_order or args.ader_vs_rk or args.host_round_trip or args.stream
+               or args.shock_workload or args.vortex128)
+    # the CPU baseline runs before this process touches the GPU
+    cpu = None if (special or args.no_cpu_baseline) else cpu_baseline_c5(args.cpu_seconds)
+
+    import torch
+    from paper_2211_13295_amd import hog
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    hog.load()
+    if args.gate_ablation:
+        steps = 100 if args.gate_ablation == "multiblast256" else 200
+        print(json.dumps(gate_ablation(hog, torch, args.gate_ablation, steps, 20)), flush=True)
+        return
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)            # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        print(f"copy calibration: 3 launches of {x.numel() * 8} bytes read + written", flush=True)
+        del x, y
+    if args.second_order:
+        print(json.dumps(second_order_line(hog, torch, args)), flush=True)
+        return
+    if args.ader_vs_rk:
+        print(json.dumps(ader_vs_rk(hog, torch, args)), flush=True)
+        return
+    if args.host_round_trip:
+        print(json.dumps(host_round_trip(hog, torch, args)), flush=True)
+        return
+    if args.stream:
+        print(json.dumps(stream_vs_in_core(hog, torch, args)), flush=True)
+        return
+    if args.shock_workload:
+        steps = 100 if args.shock_workload == "multiblast256" else 200
+        print(json.dumps(shock_workload(hog, torch, args.shock_workload, steps, 20)), flush=True)
+        return
+    if args.vortex128:
+        out = vortex128_line(hog, torch, args, n=args.n or 128)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(args.order, args.cpu_seconds)
+        print(json.dumps(out), flush=True)
+        return
+    out = headline(hog, torch, args, cpu)
     print(json.dumps(out), flush=True)
 
 

@@ -166,9 +166,11 @@ def multiblast(n=256, seed=3, nblast=16, gamma=1.4, rmin=0.05, rmax=0.1,
                    meta=dict(name="multiblast", seed=seed, centres=centres, radii=radii))
 
 
-def four_quadrant(n=384, seed=5, gamma=1.4, ndim=3):
+def four_quadrant(n=384, seed=5, gamma=1.4, ndim=3, block=None):
     """Four constant states split at x = 1/2, y = 1/2 (independent of z); per
-    quadrant rho ~ U[0.5,1.5], p ~ U[0.1,1], in-plane velocity of speed ~ U[0,0.5]."""
+    quadrant rho ~ U[0.5,1.5], p ~ U[0.1,1], in-plane velocity of speed ~ U[0,0.5].
+    block = (lo, m): only the zones lo .. lo+m-1 of every axis (the same
+    values as that slice of the whole grid; outflow boundaries)."""
     rng = np.random.default_rng(seed)
     rho_q = rng.uniform(0.5, 1.5, 4)
     p_q = rng.uniform(0.1, 1.0, 4)
@@ -176,6 +178,9 @@ def four_quadrant(n=384, seed=5, gamma=1.4, ndim=3):
     th_q = rng.uniform(0.0, 2.0 * math.pi, 4)
     h = 1.0 / n
     xs = _centres(n, h, 0.0)
+    if block is not None:
+        lo, m = block
+        xs = xs[lo:lo + m]
     if ndim == 3:
         Z, Y, X = np.meshgrid(xs, xs, xs, indexing="ij")
     else:
@@ -187,10 +192,12 @@ def four_quadrant(n=384, seed=5, gamma=1.4, ndim=3):
     v = s_q[q] * np.sin(th_q[q])
     vel = (u, v, np.zeros_like(u)) if ndim == 3 else (u, v)
     U = prim_to_cons(rho, vel, p, gamma)
-    nn = (n, n, n if ndim == 3 else 1)
-    return Problem(U=U, ndim=ndim, n=nn, h=(h, h, h), origin=(0.0, 0.0, 0.0),
+    m = len(xs)
+    nn = (m, m, m if ndim == 3 else 1)
+    x0 = float(xs[0] - 0.5 * h)
+    return Problem(U=U, ndim=ndim, n=nn, h=(h, h, h), origin=(x0, x0, x0 if ndim == 3 else 0.0),
                    bc=("outflow",) * 3, gamma=gamma,
-                   meta=dict(name="four_quadrant", seed=seed, rho=rho_q, p=p_q))
+                   meta=dict(name="four_quadrant", seed=seed, rho=rho_q, p=p_q, block=block))
 
 
 def sod(n=100, axis=0, ndim=2, ntrans=4, gamma=1.4, left=(1.0, 0.0, 1.0),

@@ -3,13 +3,13 @@
  * compressible Euler equations of an ideal gas.
  *
  * One call of hog_step() performs the three-stage update the paper builds its
- * GPU codes on (arXiv 2211.13295, Sec. I.1 and Sec. II.1, Figs. 1-7):
+ * GPU codes on (arXiv 2211.13295, Sec. I.1 and Sec. II.2, Figs. 1-7):
  *   WENO reconstruction of the conserved variables in every zone,
  *   an ADER predictor that extends each zone polynomial in time,
  *   a Riemann-solver (HLLC/HLL/Rusanov) corrector with a conservative
  *   flux-difference update, and the CFL time step of the new state.
  * With order = 2 the step is instead the paper's own second-order scheme
- * (Sec. II.1, Figs. 3-7): slopes of the conserved variables from a
+ * (Sec. II.2, Figs. 3-7): slopes of the conserved variables from a
  * monotonised-central limiter with compression factor 2 for the density and
  * 1.5 for the other variables (Fig. 3), a pointwise predictor of the time
  * mode (Fig. 4; its body is not printed and is read as the Hancock step:
@@ -19,7 +19,7 @@
  * (Fig. 5), and the flux-difference update (Figs. 6-7).  It runs as one fused
  * kernel per step on the FP64 path.
  * The state lives in device memory between calls: the paper's per-step host
- * round trip of the zone means (its "U_skinny" transfer, Sec. II.1, Fig. 1)
+ * round trip of the zone means (its "U_skinny" transfer, Sec. II.2, Fig. 1)
  * only happens when the caller asks for it with hog_get_state().
  *
  * Conventions
@@ -149,13 +149,16 @@ int hog_create(const hog_config* cfg, void* workspace, size_t bytes, void* hip_s
 int hog_destroy(hog_grid* g);
 
 /* Copy the interior state in (layout HOG_SOA | HOG_AOS, buffer on HOG_HOST |
- * HOG_DEVICE, nv*nx*ny*nz doubles).  Stream-ordered; host buffers are copied
- * before return.  Also evaluates the CFL reduction of the new state.
+ * HOG_DEVICE, nv*nx*ny*nz doubles): the `update device(U_skinny)` and
+ * U_Skinny_to_U of Fig. 1 (Sec. II.2), done once instead of every step.
+ * Stream-ordered; host buffers are copied before return.  Also evaluates the
+ * CFL reduction of the new state.
  * Errors: HOG_EINVAL, HOG_EDEVICE. */
 int hog_set_state(hog_grid* g, const double* U, int layout, int where);
 
-/* Copy the current interior state out (same layouts).  For a host buffer the
- * call synchronises the stream.  Errors: HOG_EINVAL, HOG_ESTATE, HOG_EDEVICE. */
+/* Copy the current interior state out (same layouts): the `update
+ * host(U_skinny)` of Fig. 1 (Sec. II.2), only when the caller asks for it.
+ * For a host buffer the call synchronises the stream.  Errors: HOG_EINVAL, HOG_ESTATE, HOG_EDEVICE. */
 int hog_get_state(hog_grid* g, double* U, int layout, int where);
 
 /* Like hog_set_state (SoA only) for a grid whose last axis is HOG_EXTERNAL:
@@ -167,7 +170,8 @@ int hog_get_state(hog_grid* g, double* U, int layout, int where);
 int hog_set_state_ext(hog_grid* g, const double* U, int where);
 
 /* CFL time step of the current state, dt = cfl / max_zones sum_d
- * (|u_d| + c) / dx_d (paper Fig. 7, Eval_Tstep_Ptwise with a min reduction).
+ * (|u_d| + c) / dx_d (Fig. 7 of Sec. II.2: Eval_Tstep_Ptwise per zone with a
+ * min reduction into dt_next; its body is not printed, the sum form is used).
  * Synchronises.  Errors: HOG_ENONPHYS (see hog_last_bad_zone), HOG_ESTATE. */
 int hog_compute_dt(hog_grid* g, double* dt);
 
@@ -179,15 +183,23 @@ int hog_compute_dt(hog_grid* g, double* dt);
  * Errors: HOG_EINVAL (dt <= 0 or not finite), HOG_ESTATE, HOG_ENONPHYS. */
 int hog_step(hog_grid* g, double dt, double* dt_next);
 
-/* Advance with the CFL time step computed on the device from each state (no
- * host round trip per step).  t_end <= 0: exactly nsteps steps.  t_end > 0:
+/* The time loop of Fig. 1 (Sec. II.2: DO i_timestep, dt = dt_next) run on the
+ * device: advance with the CFL time step computed on the device from each
+ * state (no host round trip per step).  t_end <= 0: exactly nsteps steps.  t_end > 0:
  * steps until the accumulated time reaches t_end, clipping the last step
  * (this mode synchronises once per step); nsteps is then an upper bound.
  * *t_out (may be NULL) receives the time advanced.  Synchronises at the end
- * and checks the final state.  Errors: HOG_EINVAL, HOG_ESTATE, HOG_ENONPHYS. */
+ * and checks the final state.  If a step produces a non-physical state the
+ * later steps of the run write nothing, and the call returns HOG_ENONPHYS
+ * with the state before that step as the current one (as hog_step does) and
+ * the first non-physical zone of that step in hog_last_bad_zone().
+ * Errors: HOG_EINVAL, HOG_ESTATE, HOG_ENONPHYS. */
 int hog_advance(hog_grid* g, int nsteps, double t_end, double* t_out);
 
-/* Copy an intermediate of the last step to host memory dst (HOG_TAP_*).
+/* Copy an intermediate of the last step to host memory dst (HOG_TAP_*): the
+ * spatial modes the reconstruction (Limiter of Figs. 1 and 3) leaves in
+ * U(:,:,:,:,1:4), the space-time modes of the predictor (Figs. 1 and 4) and
+ * the face fluxes of Make_Flux_X/Y/Z (Fig. 5), for tests.
  * Synchronises.  Errors: HOG_EINVAL (unknown tap, bytes too small, tap not
  * kept), HOG_ESTATE (no step yet). */
 int hog_debug_tap(hog_grid* g, int tap, void* dst, size_t bytes);
@@ -218,7 +230,7 @@ int hog_profile_read(hog_grid* g, double* ms, int* launches, int nstages);
 int hog_stats(hog_grid* g, double* t, double* dt, long long* fallback_zones);
 
 /* ---------------------------------------------------------------------
- * Slab streaming of a host-resident mesh (Sec. II.2 and Sec. V: each patch of
+ * Slab streaming of a host-resident mesh (Sec. II.1 and Sec. V: each patch of
  * a mesh larger than the GPU's memory is moved to the GPU every step).  The
  * mesh, of any size along its last axis, lives in two pinned host buffers;
  * every step moves it through the GPU in slabs of at most slab_planes planes
@@ -305,8 +317,9 @@ int hog_set_gate_flags(hog_grid* g, const unsigned char* flags);
  * feature-major to features (device, nf*n floats, [feature][sample]) and, to
  * maxdev (device, n floats), the largest |omega_k/gamma_k - 1| of the
  * nonlinear WENO weights over the variables and the 1D applications centred
- * at the zone (a zone is labelled smooth when it is <= 0.25).  Stream-ordered,
- * no synchronisation.  Errors: HOG_EINVAL (also at order 2), HOG_ESTATE. */
+ * at the zone (a zone is labelled smooth when it is <= 0.25).  An index
+ * outside [0, nx*ny*nz) reads nothing and yields NaN features and a NaN
+ * maxdev for that sample.  Stream-ordered, no synchronisation.  Errors: HOG_EINVAL (also at order 2), HOG_ESTATE. */
 int hog_harvest(hog_grid* g, const long long* zones, long long n, float* features, float* maxdev);
 
 /* Training of the gate network on the GPU (FP32 masters, Adam, BF16-rounded

@@ -6,7 +6,7 @@
  * CPU-baseline leg of the benchmark may load or call this library.  It shares
  * no code, header, table or constant generator with the GPU library.
  *
- * What it computes (paper, Sec. I.1 and Sec. II.1, Fig. 1): per time step
+ * What it computes (paper, Sec. I.1 and Sec. II.2, Fig. 1): per time step
  *   (1) ghost zones (Fig. 1, Boundary_Conditions),
  *   (2) WENO reconstruction of the conserved variables in every zone
  *       (Sec. I.1: reconstruction done directly on the conserved variables),
@@ -907,7 +907,7 @@ static void face_flux(const ocfg *c, int dir, const double *qa, const double *qb
 }
 
 /* ------------------------------------------------------------------------ */
-/* Second-order scheme (Sec. II.1, Figs. 3-7)                                */
+/* Second-order scheme (Sec. II.2, Figs. 3-7)                                */
 /* ------------------------------------------------------------------------ */
 /* Monotonised-central limiter with a compression factor (Fig. 3): the
  * limited undivided slope from the forward difference a and the backward

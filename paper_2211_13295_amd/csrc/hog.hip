@@ -529,6 +529,68 @@ double smax_of(const StepInfo& si)
     return s;
 }
 
+// The current device must be a gfx950 GPU; *cus receives its compute units.
+int device_check(int* cus)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(HOG_EDEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    *cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    return HOG_OK;
+}
+
+// Point a handle at the pieces of a workspace laid out by plan() and set its
+// scheme constants.  Enqueues nothing and allocates nothing.
+void bind_grid(hog_grid* g, const hog_config* cfg, const Plan& P, char* ws, size_t bytes, hipStream_t stream,
+               int cus)
+{
+    g->cfg = *cfg;
+    g->P = P;
+    g->cus = cus;
+    g->stream = stream;
+    g->ws = ws;
+    g->ws_bytes = bytes;
+    g->cur = 0;
+    g->have_state = g->have_step = g->smax_valid = false;
+    g->profiling = false;
+    g->last_bad = -1;
+    g->h[0] = cfg->dx; g->h[1] = cfg->dy; g->h[2] = (P.nd == 3) ? cfg->dz : 1.0;
+    g->wa.eps = cfg->weno_eps > 0.0 ? cfg->weno_eps : 1e-12;
+    const bool g3zero = cfg->g3[0] == 0.0 && cfg->g3[1] == 0.0 && cfg->g3[2] == 0.0;
+    const bool g4zero = cfg->g4[0] == 0.0 && cfg->g4[1] == 0.0 && cfg->g4[2] == 0.0 && cfg->g4[3] == 0.0;
+    if (P.p == 2) {
+        const double d3[3] = {0.075, 0.85, 0.075};
+        for (int i = 0; i < 3; ++i) g->wa.g[i] = g3zero ? d3[i] : cfg->g3[i];
+        g->wa.g[3] = 0.0;
+    } else {
+        const double d4[4] = {0.85, 0.01125, 0.1275, 0.01125};
+        for (int i = 0; i < 4; ++i) g->wa.g[i] = g4zero ? d4[i] : cfg->g4[i];
+    }
+    g->wa.linear = cfg->linear_weno ? 1 : 0;
+    g->info = reinterpret_cast<StepInfo*>(ws + P.off_info);
+    g->U[0] = reinterpret_cast<double*>(ws + P.off_U[0]);
+    g->U[1] = reinterpret_cast<double*>(ws + P.off_U[1]);
+    g->A = (P.p > 1) ? ws + P.off_A : nullptr;
+    g->B = (P.p > 1) ? ws + P.off_B : nullptr;
+    g->W = (P.p > 1) ? ws + P.off_W : nullptr;
+    g->FP = (P.p > 1) ? ws + P.off_FP : nullptr;
+    for (int d = 0; d < 3; ++d)
+        g->F[d] = (d < P.nd && (P.p > 1 || cfg->debug)) ? reinterpret_cast<double*>(ws + P.off_F[d]) : nullptr;
+    g->Q = cfg->debug ? static_cast<void*>(ws + P.off_Q) : nullptr;
+    g->stage = reinterpret_cast<double*>(ws + P.off_stage);
+    for (int k = 0; k < 6; ++k) {
+        g->S[k] = (k >= 1 && k < P.nstages) ? reinterpret_cast<double*>(ws + P.off_S[k]) : nullptr;
+        g->Lb[k] = (k < P.nstages) ? reinterpret_cast<double*>(ws + P.off_L[k]) : nullptr;
+    }
+    g->gate_on = g->gate_fixed = g->gate_net = false;
+    g->gate = ws + P.off_gate;
+    g->flags = reinterpret_cast<unsigned char*>(ws + P.off_flags);
+    g->logits = reinterpret_cast<float*>(ws + P.off_logits);
+}
+
 } // namespace
 
 extern "C" {
@@ -560,56 +622,12 @@ int hog_create(const hog_config* cfg, void* workspace, size_t bytes, void* hip_s
     Plan P;
     plan(cfg, &P);
     if (bytes < P.total) return fail(HOG_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, P.total);
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    HIP_TRY(hipGetDeviceProperties(&prop, dev));
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return fail(HOG_EDEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    int cus = 0;
+    rc = device_check(&cus);
+    if (rc) return rc;
     hog_grid* g = new (std::nothrow) hog_grid();
     if (!g) return fail(HOG_ENOMEM, "host allocation failed");
-    g->cfg = *cfg;
-    g->P = P;
-    g->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    g->stream = static_cast<hipStream_t>(hip_stream);
-    g->ws = static_cast<char*>(workspace);
-    g->ws_bytes = bytes;
-    g->cur = 0;
-    g->have_state = g->have_step = g->smax_valid = false;
-    g->profiling = false;
-    g->last_bad = -1;
-    g->h[0] = cfg->dx; g->h[1] = cfg->dy; g->h[2] = (P.nd == 3) ? cfg->dz : 1.0;
-    g->wa.eps = cfg->weno_eps > 0.0 ? cfg->weno_eps : 1e-12;
-    const bool g3zero = cfg->g3[0] == 0.0 && cfg->g3[1] == 0.0 && cfg->g3[2] == 0.0;
-    const bool g4zero = cfg->g4[0] == 0.0 && cfg->g4[1] == 0.0 && cfg->g4[2] == 0.0 && cfg->g4[3] == 0.0;
-    if (P.p == 2) {
-        const double d3[3] = {0.075, 0.85, 0.075};
-        for (int i = 0; i < 3; ++i) g->wa.g[i] = g3zero ? d3[i] : cfg->g3[i];
-        g->wa.g[3] = 0.0;
-    } else {
-        const double d4[4] = {0.85, 0.01125, 0.1275, 0.01125};
-        for (int i = 0; i < 4; ++i) g->wa.g[i] = g4zero ? d4[i] : cfg->g4[i];
-    }
-    g->wa.linear = cfg->linear_weno ? 1 : 0;
-    g->info = reinterpret_cast<StepInfo*>(g->ws + P.off_info);
-    g->U[0] = reinterpret_cast<double*>(g->ws + P.off_U[0]);
-    g->U[1] = reinterpret_cast<double*>(g->ws + P.off_U[1]);
-    g->A = (P.p > 1) ? g->ws + P.off_A : nullptr;
-    g->B = (P.p > 1) ? g->ws + P.off_B : nullptr;
-    g->W = (P.p > 1) ? g->ws + P.off_W : nullptr;
-    g->FP = (P.p > 1) ? g->ws + P.off_FP : nullptr;
-    for (int d = 0; d < 3; ++d)
-        g->F[d] = (d < P.nd && (P.p > 1 || cfg->debug)) ? reinterpret_cast<double*>(g->ws + P.off_F[d]) : nullptr;
-    g->Q = cfg->debug ? static_cast<void*>(g->ws + P.off_Q) : nullptr;
-    g->stage = reinterpret_cast<double*>(g->ws + P.off_stage);
-    for (int k = 0; k < 6; ++k) {
-        g->S[k] = (k >= 1 && k < P.nstages) ? reinterpret_cast<double*>(g->ws + P.off_S[k]) : nullptr;
-        g->Lb[k] = (k < P.nstages) ? reinterpret_cast<double*>(g->ws + P.off_L[k]) : nullptr;
-    }
-    g->gate_on = g->gate_fixed = g->gate_net = false;
-    g->gate = g->ws + P.off_gate;
-    g->flags = reinterpret_cast<unsigned char*>(g->ws + P.off_flags);
-    g->logits = reinterpret_cast<float*>(g->ws + P.off_logits);
+    bind_grid(g, cfg, P, static_cast<char*>(workspace), bytes, static_cast<hipStream_t>(hip_stream), cus);
     k_reset<<<1, 1, 0, g->stream>>>(g->info, 0.0, 1);
     rc = launch_check("reset");
     if (rc) { delete g; return rc; }
@@ -788,7 +806,8 @@ int hog_advance(hog_grid* g, int nsteps, double t_end, double* t_out)
         if (rc) return rc;
         g->smax_valid = true;
     }
-    // reset the time accumulator without touching the CFL reduction
+    // reset the time accumulator without touching the CFL reduction, and make
+    // a non-physical state halt the run (later steps of it write no new state)
     {
         StepInfo si;
         rc = read_info(g, &si);
@@ -799,33 +818,40 @@ int hog_advance(hog_grid* g, int nsteps, double t_end, double* t_out)
         }
         si.t = 0.0;
         si.t_end = t_end > 0.0 ? t_end : 0.0;
+        si.nstep = 0ull;
+        si.sticky = 1;
+        si.halted = 0;
         HIP_TRY(hipMemcpyAsync(g->info, &si, sizeof si, hipMemcpyHostToDevice, g->stream));
         HIP_TRY(hipStreamSynchronize(g->stream));
     }
-    double t = 0.0;
+    const int cur0 = g->cur;
+    StepInfo si;
     for (int s = 0; s < nsteps; ++s) {
         rc = enqueue_step(g, -1.0);
         if (rc) return rc;
         g->cur ^= 1;
         g->have_step = true;
         if (t_end > 0.0) {
-            StepInfo si;
             rc = read_info(g, &si);
             if (rc) return rc;
-            t = si.t;
-            if (si.bad != ULLONG_MAX) {
-                g->last_bad = (long long)si.bad;
-                return fail(HOG_ENONPHYS, "non-physical state in zone %lld", g->last_bad);
-            }
-            if (t >= t_end * (1.0 - 1e-14) || si.dt <= 0.0) break;
+            if (si.bad != ULLONG_MAX) break;
+            if (si.t >= t_end * (1.0 - 1e-14) || si.dt <= 0.0) break;
         }
     }
-    StepInfo si;
     rc = read_info(g, &si);
     if (rc) return rc;
+    k_arm<<<1, 1, 0, g->stream>>>(g->info, 0);
+    rc = launch_check("arm");
+    if (rc) return rc;
     if (si.bad != ULLONG_MAX) {
+        // step nstep - 1 (counted from 0) made the non-physical state; its
+        // input, the last admissible state, is still in its buffer
+        const unsigned long long f = si.nstep > 0 ? si.nstep - 1 : 0;
+        g->cur = cur0 ^ (int)(f & 1ull);
+        g->smax_valid = false;
         g->last_bad = (long long)si.bad;
-        return fail(HOG_ENONPHYS, "non-physical state in zone %lld", g->last_bad);
+        return fail(HOG_ENONPHYS, "step %llu of the run produced a non-physical state in zone %lld; the state "
+                                  "before that step is kept", f + 1, g->last_bad);
     }
     g->last_bad = -1;
     if (t_out) *t_out = si.t;
@@ -1524,3 +1550,4 @@ int hog_stream_step(hog_stream* s, double dt, double* dt_next)
 }
 
 } // extern "C"
+

@@ -238,6 +238,13 @@ __global__ __launch_bounds__(256) void k_harvest(const double* __restrict__ U, P
     const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const long long z = zones[s];
+    if (z < 0 || z >= box_size(I)) {      // not an interior zone: NaN sample, nothing read
+        const float nan = __builtin_nanf("");
+#pragma unroll
+        for (int q = 0; q < G::NF; ++q) feat[(long long)q * n + s] = nan;
+        maxdev[s] = nan;
+        return;
+    }
     int i, j, k;
     box_ijk(I, z, i, j, k);
     float f[G::NF];

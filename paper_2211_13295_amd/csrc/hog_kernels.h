@@ -57,7 +57,11 @@ struct StepInfo {
     unsigned long long smax_bits;   // bits of max_zones sum_d (|u_d| + c) / dx_d (>= 0)
     unsigned long long bad;         // first non-physical zone, ULLONG_MAX if none
     unsigned long long fallback;    // predictor zones that used the positivity fallback
-    double pad_[7];
+    unsigned long long nstep;       // steps begun since the last arm (k_arm), not counting halted ones
+    int sticky;                     // 1 inside a device-side run of steps: a non-physical state halts it
+    int halted;                     // 1: a step of this run produced a non-physical state; later steps
+                                    //    of the run write no new state
+    double pad_[5];
 };
 
 // ------------------------------------------------------------------------
@@ -65,6 +69,11 @@ struct StepInfo {
 // ------------------------------------------------------------------------
 __global__ void k_begin_step(StepInfo* info, double dt_user, double cfl, double h0, double h1, double h2)
 {
+    if (info->sticky && info->bad != ULLONG_MAX) {   // keep the first failure and the state before it
+        info->halted = 1;
+        return;
+    }
+    info->nstep += 1;
     double dt = dt_user;
     if (!(dt > 0.0)) dt = cfl / __longlong_as_double((long long)info->smax_bits);
     if (info->t_end > 0.0) {
@@ -83,9 +92,23 @@ __global__ void k_begin_step(StepInfo* info, double dt_user, double cfl, double 
 
 __global__ void k_reset(StepInfo* info, double t_end, int reset_time)
 {
-    if (reset_time) { info->t = 0.0; info->t_end = t_end; }
+    if (reset_time) {
+        info->t = 0.0;
+        info->t_end = t_end;
+        info->nstep = 0ull;
+        info->sticky = 0;
+        info->halted = 0;
+    }
     info->smax_bits = 0ull;
     info->bad = ULLONG_MAX;
+}
+
+// Start (sticky = 1) or end (sticky = 0) a device-side run of steps.
+__global__ void k_arm(StepInfo* info, int sticky)
+{
+    info->sticky = sticky;
+    info->halted = 0;
+    info->nstep = 0ull;
 }
 
 // ------------------------------------------------------------------------
@@ -1247,6 +1270,7 @@ __global__ __launch_bounds__(256) void k_update(const double* __restrict__ Uo, d
                                                 double gamma, double ih0, double ih1, double ih2)
 {
     constexpr int NV = D + 2;
+    if (info->halted) return;                   // uniform: the run stopped at a non-physical state
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0.0;
     bool ok = true;

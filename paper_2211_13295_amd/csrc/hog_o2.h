@@ -1,4 +1,4 @@
-// hog_o2.h -- the second-order scheme of Sec. II.1 (Figs. 3-7) as one fused
+// hog_o2.h -- the second-order scheme of Sec. II.2 (Figs. 3-7) as one fused
 // gfx950 kernel per step: MC-limited slopes of the conserved variables
 // (Fig. 3), the pointwise predictor of the time mode (Fig. 4, read as the
 // Hancock step of MUSCL-Hancock), the face states at the face centre and half
@@ -148,6 +148,9 @@ __global__ __launch_bounds__(O2Shape<D>::NT, O2Shape<D>::MINB) void k_o2_step(co
     __shared__ double sYp[NV][E];
     __shared__ double sFy[NV][E];
 
+    if constexpr (!RK) {
+        if (info->halted) return;               // uniform: the run stopped at a non-physical state
+    }
     // block -> (column tile, march chunk); the blocks of one XCD take a contiguous range
     const int n0 = a.n[0], n1 = a.n[1];
     const int nm = a.n[D - 1];                      // zones along the march axis

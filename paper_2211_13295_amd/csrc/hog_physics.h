@@ -1,7 +1,7 @@
 // hog_physics.h -- pointwise device routines of the ADER-WENO Euler update:
 // equation of state, physical fluxes, Riemann solvers and the 1D WENO
 // operator.  These are the "routine seq" pieces of the paper's structure
-// (Sec. II.1: Predictor_Ptwise, Riemann_Solver_Ptwise, Eval_Tstep_Ptwise),
+// (Sec. II.2: Predictor_Ptwise, Riemann_Solver_Ptwise, Eval_Tstep_Ptwise),
 // written as inlined device functions on registers.
 #pragma once
 #include <hip/hip_runtime.h>

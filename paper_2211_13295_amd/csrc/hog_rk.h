@@ -141,6 +141,7 @@ __global__ __launch_bounds__(256) void k_rk_combine(Pad p, Box I, const double* 
                                                     int last, double gamma, double ih0, double ih1, double ih2)
 {
     constexpr int NV = D + 2;
+    if (last && info->halted) return;           // uniform: the run stopped at a non-physical state
     const long long N = box_size(I);
     const long long z = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     double s = 0.0;

@@ -305,7 +305,10 @@ class Grid:
     def harvest(self, zones):
         """Features (n, nf) and max weight deviation (n,) of interior zones (flat indices)."""
         torch = self._torch
-        z = torch.as_tensor(np.asarray(zones, dtype=np.int64), device="cuda")
+        zn = np.asarray(zones, dtype=np.int64)
+        if zn.size and (zn.min() < 0 or zn.max() >= self.nzones):
+            raise ValueError(f"zone indices must lie in [0, {self.nzones})")
+        z = torch.as_tensor(zn, device="cuda")
         n = z.numel()
         nf = (self.ndim + 2) * (4 * self.ndim + 1)
         feat = torch.empty(nf * max(n, 1), dtype=torch.float32, device="cuda")

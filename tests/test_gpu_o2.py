@@ -1,4 +1,4 @@
-"""Parity of the fused second-order kernel (Sec. II.1, Figs. 3-7) with the
+"""Parity of the fused second-order kernel (Sec. II.2, Figs. 3-7) with the
 oracle's second-order scheme, through the C ABI.
 
 Same bar as the higher orders: relative L1 <= 1e-12 over all variables and

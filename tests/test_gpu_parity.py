@@ -357,3 +357,42 @@ def test_error_paths(hog):
     assert e.value.code == hog.HOG_ENONPHYS
     np.testing.assert_array_equal(g.get_state(), sm.U)
     assert g.compute_dt() > 0
+
+
+@pytest.mark.parametrize("t_end", [0.0, 10.0])
+def test_advance_keeps_the_state_before_a_failing_step(hog, t_end):
+    """A device-side run of steps that meets a non-physical state stops there:
+    hog_advance returns HOG_ENONPHYS with the state before the failing step
+    current and the failing step's first bad zone, like the same steps taken
+    one at a time with hog_step; the handle then steps normally again.  The
+    workload (a cold rarefying flow at fourth order without the positivity
+    fallback) fails in its third step on the oracle too."""
+    pb = icgen.cold_wave(n=32, ndim=2, amp=2.0, p0=1e-3)
+    c = oracle.cfg_from_problem(pb, 4, positivity=False)
+    U = pb.U
+    for s in range(2):
+        U = oracle.step(c, U, oracle.cfl_dt(c, U)[0])
+        assert oracle.cfl_dt(c, U)[1] < 0
+    assert oracle.cfl_dt(c, oracle.step(c, U, oracle.cfl_dt(c, U)[0]))[1] >= 0
+    g = grid_for(hog, pb, 4, positivity=False)
+    states = [pb.U]
+    failed_at, bad_zone = None, None
+    for s in range(10):
+        try:
+            g.step(g.compute_dt())
+        except hog.HogError as e:
+            assert e.code == hog.HOG_ENONPHYS
+            failed_at, bad_zone = s, g.last_bad_zone()
+            break
+        states.append(g.get_state())
+    assert failed_at == 2 and bad_zone >= 0
+    g2 = grid_for(hog, pb, 4, positivity=False)
+    with pytest.raises(hog.HogError) as e:
+        g2.advance(10, t_end=t_end)
+    assert e.value.code == hog.HOG_ENONPHYS
+    assert g2.last_bad_zone() == bad_zone
+    np.testing.assert_array_equal(g2.get_state(), states[failed_at])
+    # the run is over: the handle steps and advances as usual from a new state
+    g2.set_state(pb.U)
+    assert g2.advance(2) > 0
+    np.testing.assert_array_equal(g2.get_state(), states[2])

@@ -1,4 +1,4 @@
-"""Pins of the oracle's second-order scheme (Sec. II.1, Figs. 3-7): the MC
+"""Pins of the oracle's second-order scheme (Sec. II.2, Figs. 3-7): the MC
 limiter against its ratio form, the Hancock predictor against the exact time
 derivative of linear advection, the reduction to the first-order Godunov
 scheme where every slope is limited away, conservation, symmetry, the Sod
