@@ -31,7 +31,9 @@
  *    double U[nz][ny][nx][nv] (the paper's zone-mean array order).
  *  - Device memory: the caller allocates one workspace of
  *    hog_workspace_size() bytes (e.g. a torch uint8 tensor) and keeps it alive
- *    as long as the handle; the library allocates no device memory itself.
+ *    as long as the handle; the library allocates no device memory itself
+ *    (hog_step_static instead uses a fixed array that every GPU the library
+ *    runs on holds from the library's load).
  *  - Stream: all work is enqueued on the hipStream_t given at hog_create();
  *    calls return without synchronising unless stated.  One handle must not
  *    be used from two threads at once.
@@ -343,6 +345,32 @@ int hog_mlp_grads(hog_mlp* m, const float* X, const float* y, const float* w, in
 int hog_mlp_step(hog_mlp* m, const float* X, const float* y, const float* w, int n, float lr, float* loss);
 /* Logits of n samples (device output). */
 int hog_mlp_predict(hog_mlp* m, const float* X, int n, float* logits);
+
+/* ---------------------------------------------------------------------
+ * One step without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels as hog_step, with the workspace in a
+ * fixed-size device array inside the library instead of a caller's buffer.
+ * U_in and U_out are device arrays of the interior state, SoA
+ * [nv][nz][ny][nx] doubles, owned by the caller; they may be the same array
+ * (U_in is copied in before anything is written).  The step is enqueued on
+ * hip_stream (NULL = default stream).  If dt_next is not NULL the call
+ * synchronises, checks the new state and returns its CFL time step; on a
+ * non-physical new state it returns HOG_ENONPHYS and leaves U_out untouched.
+ * If dt_next is NULL nothing is checked and the call does not synchronise.
+ * The config may not use HOG_EXTERNAL boundaries or debug taps; no gate.
+ * Limit: hog_workspace_size(cfg) must not exceed hog_step_static_capacity()
+ * bytes (256 MiB: up to 40^3 zones at fourth order in 3D FP64, 520^2 at
+ * third order in 2D); larger grids get HOG_ENOMEM and need hog_create.
+ * Each GPU holds one copy of the array from the library's load to the end of
+ * the process, shared by every call on that GPU: calls that overlap on one
+ * GPU (two streams or threads at once) race and must be serialised by the
+ * caller.  No host or device memory is allocated by the call.
+ * Errors: HOG_EINVAL, HOG_ENOMEM (grid too large), HOG_ENONPHYS, HOG_EDEVICE.
+ * --------------------------------------------------------------------- */
+size_t hog_step_static_capacity(void);
+int hog_step_static(const hog_config* cfg, const double* U_in, double* U_out, double dt, double* dt_next,
+                    void* hip_stream);
 
 /* Zone index (x fastest) of the first non-physical zone found by the last
  * check, or -1. */

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "hog.h"
@@ -1551,3 +1552,98 @@ int hog_stream_step(hog_stream* s, double dt, double* dt_next)
 
 } // extern "C"
 
+// ------------------------------------------------------------------------
+// One step with no device allocation: the workspace is a file-scope device
+// array of a fixed size instead of a caller's buffer.  Each GPU the library
+// runs on holds its own copy of the array from the module load to the end of
+// the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name is a host-side
+// stand-in, not a device address).
+// ------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = size_t(256) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices];   // device address of scratch per device (null: not looked up yet)
+int g_scratch_cus[kMaxDevices];
+
+// Device address of the scratch array on the current device, looked up (and
+// the device checked) on the first call on that device.
+int scratch_on_current_device(char** ptr, int* cus)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HOG_EDEVICE, "device index %d is out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int c = 0;
+        int rc = device_check(&c);
+        if (rc) return rc;
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || reinterpret_cast<uintptr_t>(p) % kAlign)
+            return fail(HOG_EDEVICE, "scratch array of device %d is not 256-byte aligned", dev);
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+        g_scratch_cus[dev] = c;
+    }
+    *ptr = g_scratch_ptr[dev];
+    *cus = g_scratch_cus[dev];
+    return HOG_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+size_t hog_step_static_capacity(void) { return kScratchBytes; }
+
+int hog_step_static(const hog_config* cfg, const double* U_in, double* U_out, double dt, double* dt_next,
+                    void* hip_stream)
+{
+    g_err[0] = 0;
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (!U_in || !U_out) return fail(HOG_EINVAL, "NULL state pointer");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(HOG_EINVAL, "dt must be finite and > 0 (got %g)", dt);
+    for (int d = 0; d < 3; ++d)
+        if (cfg->bc[d] == HOG_EXTERNAL)
+            return fail(HOG_EINVAL, "an external boundary needs hog_set_state_ext on a handle");
+    if (cfg->debug) return fail(HOG_EINVAL, "debug taps need a handle (hog_create)");
+    Plan P;
+    plan(cfg, &P);
+    if (P.total > kScratchBytes)
+        return fail(HOG_ENOMEM, "this grid needs %zu workspace bytes; hog_step_static holds at most %zu "
+                                "(use hog_create with a caller workspace)", P.total, kScratchBytes);
+    char* ws = nullptr;
+    int cus = 0;
+    rc = scratch_on_current_device(&ws, &cus);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hog_grid g{};
+    bind_grid(&g, cfg, P, ws, kScratchBytes, s, cus);
+    // the array keeps the previous call's contents: reset the step scalars
+    k_reset<<<1, 1, 0, s>>>(g.info, 0.0, 1);
+    const long long N = box_size(P.I);
+    if (P.nd == 3) k_pack<3><<<nblocks(N, 256), 256, 0, s>>>(U_in, g.U[0], P.pad, P.I, 0);
+    else k_pack<2><<<nblocks(N, 256), 256, 0, s>>>(U_in, g.U[0], P.pad, P.I, 0);
+    rc = launch_check("pack");
+    if (rc) return rc;
+    rc = enqueue_step(&g, dt);
+    if (rc) return rc;
+    if (dt_next) {
+        StepInfo si;
+        rc = read_info(&g, &si);
+        if (rc) return rc;
+        if (si.bad != ULLONG_MAX)
+            return fail(HOG_ENONPHYS, "step produced a non-physical state in zone %lld", (long long)si.bad);
+        *dt_next = cfg->cfl / smax_of(si);
+    }
+    if (P.nd == 3) k_unpack<3><<<nblocks(N, 256), 256, 0, s>>>(g.U[1], U_out, P.pad, P.I, 0);
+    else k_unpack<2><<<nblocks(N, 256), 256, 0, s>>>(g.U[1], U_out, P.pad, P.I, 0);
+    return launch_check("unpack");
+}
+
+} // extern "C"

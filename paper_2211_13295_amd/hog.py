@@ -96,6 +96,9 @@ def load():
               "hog_mlp_create", "hog_mlp_destroy", "hog_mlp_set_params", "hog_mlp_get_params", "hog_mlp_grads",
               "hog_mlp_step", "hog_mlp_predict"):
         getattr(L, f).restype = C.c_int
+    L.hog_step_static.argtypes = [cp, vp, vp, C.c_double, C.POINTER(C.c_double), vp]
+    L.hog_step_static.restype = C.c_int
+    L.hog_step_static_capacity.restype = C.c_size_t
     L.hog_last_bad_zone.argtypes = [vp]
     L.hog_last_bad_zone.restype = C.c_longlong
     for f in ("hog_set_state_ext", "hog_stream_workspace_size", "hog_stream_create", "hog_stream_destroy",
@@ -146,6 +149,32 @@ def workspace_size(cfg):
     n = C.c_size_t(0)
     _check(load().hog_workspace_size(C.byref(cfg), C.byref(n)))
     return n.value
+
+
+def step_static_capacity():
+    """Workspace bytes the no-allocation step holds (hog_step_static_capacity)."""
+    return int(load().hog_step_static_capacity())
+
+
+def step_static(cfg, U_in, U_out, dt, want_next=True):
+    """hog_step_static: one step of the interior state U_in (a CUDA float64
+    tensor, SoA [nv][nz][ny][nx], contiguous) into U_out (same shape; may be
+    U_in) on torch's current stream, with the library's own fixed device
+    scratch array as workspace (no allocation).  Returns dt_next, or None
+    when want_next is False (then nothing is checked or synchronised)."""
+    import torch
+    for t in (U_in, U_out):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("U_in and U_out must be contiguous float64 CUDA tensors")
+    nv = cfg.ndim + 2
+    n = nv * cfg.nx * cfg.ny * (cfg.nz if cfg.ndim == 3 else 1)
+    if U_in.numel() != n or U_out.numel() != n:
+        raise ValueError(f"state tensors must hold {n} doubles")
+    nxt = C.c_double(0.0)
+    stream = torch.cuda.current_stream().cuda_stream
+    _check(load().hog_step_static(C.byref(cfg), C.c_void_p(U_in.data_ptr()), C.c_void_p(U_out.data_ptr()),
+                                  float(dt), C.byref(nxt) if want_next else None, C.c_void_p(stream)))
+    return nxt.value if want_next else None
 
 
 class Grid:

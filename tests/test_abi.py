@@ -98,3 +98,23 @@ def test_stepper_external_and_stream_configs_without_a_device():
     for slab, cfg in ((0, mesh), (21, mesh), (6, hog.make_config(3, (8, 8, 20), 4, (0.1,) * 3, stepper="rk3")),
                       (6, ext)):
         assert L.hog_stream_workspace_size(ctypes.byref(cfg), slab, ctypes.byref(nb)) == hog.HOG_EINVAL
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhog.so not built")
+def test_static_step_rejects_grids_beyond_its_array_without_a_device():
+    """hog_step_static checks the configuration and its workspace size against
+    the fixed array before any device call (the state pointers are not read on
+    that path)."""
+    from paper_2211_13295_amd import hog
+    L = hog.load()
+    cap = hog.step_static_capacity()
+    assert cap == 256 << 20
+    big = hog.make_config(3, (41, 41, 41), 4, (0.1, 0.1, 0.1))
+    fits = hog.make_config(3, (40, 40, 40), 4, (0.1, 0.1, 0.1))
+    assert hog.workspace_size(fits) <= cap < hog.workspace_size(big)
+    dummy = ctypes.c_void_p(256)
+    assert L.hog_step_static(ctypes.byref(big), dummy, dummy, 1e-3, None, None) == hog.HOG_ENOMEM
+    assert "at most" in L.hog_last_error().decode()
+    ext = hog.make_config(3, (8, 8, 8), 4, (0.1, 0.1, 0.1), bc=("periodic", "periodic", "external"))
+    assert L.hog_step_static(ctypes.byref(ext), dummy, dummy, 1e-3, None, None) == hog.HOG_EINVAL
+    assert L.hog_step_static(ctypes.byref(fits), None, dummy, 1e-3, None, None) == hog.HOG_EINVAL
+    assert L.hog_step_static(ctypes.byref(fits), dummy, dummy, -1.0, None, None) == hog.HOG_EINVAL
