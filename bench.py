@@ -46,6 +46,11 @@ KERNEL_SOURCES_O2 = KERNEL_SOURCES + [os.path.join(ROOT, "paper_2211_13295_amd",
 KERNEL_SOURCES_RK = KERNEL_SOURCES + [os.path.join(ROOT, "paper_2211_13295_amd", "csrc", "hog_rk.h")]
 
 
+def zone_rate(zones, ms_per_step):
+    """Zone updates per second of steps over `zones` zones taking ms_per_step each."""
+    return zones / (ms_per_step * 1e-3)
+
+
 def _binom(n, k):
     return math.comb(n, k)
 
@@ -842,6 +847,44 @@ def vortex128_line(hog, torch, args, n=128):
     return out
 
 
+def gate_train_throughput(hog, torch, args):
+    """Training throughput of the gate network on the GPU's own kernels (BF16
+    MFMA forward, backward and weight gradients, FP32 Adam): Adam steps on
+    batches of 4096 samples drawn from stencils harvested from the 128^3
+    vortex workload and the 128^3 multi-blast (FP64 runs, fourth order); one
+    JSON line with samples/s."""
+    import icgen
+    feats, labels = [], []
+    for pb in (icgen.vortex3d_perturbed(n=128, seed=2), icgen.multiblast(n=128, seed=3)):
+        g = hog.Grid.from_problem(pb, 4)
+        F, dev = g.harvest(np.arange(0, pb.U[0].size, 4))
+        feats.append(F)
+        labels.append((dev <= 0.25).float())
+        g.close()
+        torch.cuda.empty_cache()
+    X = torch.cat(feats)
+    y = torch.cat(labels)
+    batch, steps = 4096, args.steps * 50
+    m = hog.Mlp(X.shape[1], batch_max=batch)
+    z = np.load(GATE_FILE)
+    m.set_params(z["params"])
+    gen = torch.Generator(device="cpu").manual_seed(0)
+    idx = torch.randint(0, X.shape[0], (steps + 10, batch), generator=gen).cuda()
+    batches = [(X[i].contiguous(), y[i].contiguous()) for i in idx[:16]]
+    for k in range(10):
+        m.step(*batches[k % 16], None, lr=1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        m.step(*batches[k % 16], None, lr=1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"metric": "gate training samples/s (Adam steps, batch 4096)", "value": steps * batch / el,
+            "unit": "samples/s", "steps": steps, "ms_per_step": el * 1e3 / steps, "batch": batch,
+            "features": int(X.shape[1]), "params": m.np,
+            "data": "stencils harvested from the 128^3 vortex and multi-blast workloads (FP64, order 4)"}
+
+
 def c5_cutout(m):
     """A bounded sample of the four-quadrant workload for the CPU oracle: the
     m^3 block of the 384^3 initial state around the domain centre, where the
@@ -957,7 +1000,7 @@ def headline(hog, torch, args, cpu):
     ms64, prof = timed(g, args.repeats)
     free(g)
     ms_step = ms64[0]
-    value = zones * K / (ms_step / 1e3)
+    value = zone_rate(zones, ms_step)
     srt = sorted(ms64)
 
     D, P = 3, order - 1
@@ -979,7 +1022,7 @@ def headline(hog, torch, args, cpu):
             g.advance(args.warmup)
         ms, prof_m = timed(g, args.repeats)
         U, _ = stepped(g, dts)
-        rec = {"value": zones * K / (ms[0] / 1e3), "unit": UNIT, "ms_per_step": ms[0],
+        rec = {"value": zone_rate(zones, ms[0]), "unit": UNIT, "ms_per_step": ms[0],
                "repeats_ms_per_step": {"n": len(ms), "median": sorted(ms)[len(ms) // 2], "min": min(ms),
                                        "max": max(ms)},
                "dtype": "f32+f64",
@@ -1069,6 +1112,8 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the predictor traffic record from two rocprofv3 counter files and exit")
     ap.add_argument("--traffic-kind", choices=["c5"], help="with --traffic-from: the headline's 384^3 record")
+    ap.add_argument("--gate-train", action="store_true",
+                    help="instead of the headline: training throughput of the gate network (samples/s)")
     args = ap.parse_args()
     if args.cpu_sample:
         cpu_sample(args.cpu_sample, args.cpu_seconds)
@@ -1084,7 +1129,7 @@ def main():
         sys.exit(2)
 
     special = (args.gate_ablation or args.second_order or args.ader_vs_rk or args.host_round_trip or args.stream
-               or args.shock_workload or args.vortex128)
+               or args.shock_workload or args.vortex128 or args.gate_train)
     # the CPU baseline runs before this process touches the GPU
     cpu = None if (special or args.no_cpu_baseline) else cpu_baseline_c5(args.cpu_seconds)
 
@@ -1122,6 +1167,9 @@ def main():
     if args.shock_workload:
         steps = 100 if args.shock_workload == "multiblast256" else 200
         print(json.dumps(shock_workload(hog, torch, args.shock_workload, steps, 20)), flush=True)
+        return
+    if args.gate_train:
+        print(json.dumps(gate_train_throughput(hog, torch, args)), flush=True)
         return
     if args.vortex128:
         out = vortex128_line(hog, torch, args, n=args.n or 128)

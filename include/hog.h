@@ -120,7 +120,11 @@ typedef struct hog_config {
                             HOG_SSPRK54: Runge-Kutta with 2, 3 or 5 stages (Table IV), each
                             stage the same reconstruction and Riemann solver with
                             face points in space only; FP64, no debug taps, no gate */
-    int reserved[2];     /* must be 0 */
+    int characteristic;  /* 1: every 1D WENO application on the characteristic fields of
+                            the flux Jacobian along its axis at the mean of its centre
+                            zone instead of on the conserved variables (orders 3 and 4,
+                            FP64; the alternative to Sec. I.1's component-wise choice) */
+    int reserved;        /* must be 0 */
     double gamma;        /* ratio of specific heats, > 1 */
     double dx, dy, dz;   /* zone widths (dz ignored in 2D), > 0 */
     double cfl;          /* CFL number of hog_compute_dt / dt_next, in (0, 1] */

@@ -17,6 +17,7 @@
 #include "hog_gate.h"
 #include "hog_o2.h"
 #include "hog_rk.h"
+#include "hog_char.h"
 
 using namespace hog;
 
@@ -84,8 +85,10 @@ int check_cfg(const hog_config* c)
         return fail(HOG_EINVAL, "precision %d not supported", c->precision);
     if (c->precision == HOG_MIXED && c->debug)
         return fail(HOG_EINVAL, "space-time mode taps are kept on the FP64 path only");
-    for (int i = 0; i < 2; ++i)
-        if (c->reserved[i] != 0) return fail(HOG_EINVAL, "reserved fields must be 0");
+    if (c->reserved != 0) return fail(HOG_EINVAL, "reserved fields must be 0");
+    if (c->characteristic != 0 && c->characteristic != 1) return fail(HOG_EINVAL, "characteristic must be 0 or 1");
+    if (c->characteristic && (c->order < 3 || c->precision != HOG_FP64))
+        return fail(HOG_EINVAL, "characteristic reconstruction runs at orders 3 and 4 on the FP64 path");
     if (c->stepper != HOG_ADER && !rk_nstages(c->stepper)) return fail(HOG_EINVAL, "unknown stepper %d", c->stepper);
     if (c->stepper != HOG_ADER && (c->precision != HOG_FP64 || c->debug))
         return fail(HOG_EINVAL, "Runge-Kutta stepping runs on the FP64 path without debug taps");
@@ -262,6 +265,32 @@ int launch_check(const char* what)
     return HOG_OK;
 }
 
+// The x -> y -> z reconstruction sweeps of the padded state Uc into the
+// spatial modes W (component-wise, or on characteristic fields).
+template <int D, int P, typename T>
+void enqueue_recon(hog_grid* g, const double* Uc, T* A, T* B, T* W, const unsigned char* gf)
+{
+    const Plan& L = g->P;
+    hipStream_t s = g->stream;
+    if constexpr (sizeof(T) == 8) {
+        if (g->cfg.characteristic) {
+            const double gam = g->cfg.gamma;
+            k_recon_x_char<D, P><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa, gam, gf,
+                                                                              L.I);
+            k_recon_y_char<D, P><<<nblocks(recon_y_threads<D, P>(L.BY) / (D + 2), 256), 256, 0, s>>>(
+                A, L.AX, L.BY, B, g->wa, gam, gf, L.I);
+            if constexpr (D == 3)
+                k_recon_z_char<P><<<nblocks(recon_z_threads<P>(L.R) / 5, 256), 256, 0, s>>>(B, L.BY, L.R, W, g->wa,
+                                                                                             gam, gf, L.I);
+            return;
+        }
+    }
+    k_recon_x<D, P, T><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa, gf, L.I);
+    k_recon_y<D, P, T><<<nblocks(recon_y_threads<D, P>(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa, gf, L.I);
+    if constexpr (D == 3)
+        k_recon_z<P, T><<<nblocks(recon_z_threads<P>(L.R), 256), 256, 0, s>>>(B, L.BY, L.R, W, g->wa, gf, L.I);
+}
+
 template <int D, int P, typename T>
 int enqueue_step_t(hog_grid* g, double dt_user)
 {
@@ -286,16 +315,12 @@ int enqueue_step_t(hog_grid* g, double dt_user)
         const unsigned char* gf = nullptr;
         if (g->gate_on && !g->gate_fixed) {
             StageMark mg(g, 5);
-            k_gate_infer<D><<<nblocks(box_size(L.I), 16), 64, 0, s>>>(
+            k_gate_infer<D><<<gate_blocks(box_size(L.I), g->cus), 64 * kGateWaves, 0, s>>>(
                 Uc, L.pad, L.I, static_cast<const GateParams<D>*>(g->gate), g->flags, nullptr);
         }
         if (g->gate_on) gf = g->flags;
         StageMark m(g, 1);
-        k_recon_x<D, P, T><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(Uc, L.pad, L.AX, A, g->wa, gf, L.I);
-        k_recon_y<D, P, T><<<nblocks(recon_y_threads<D, P>(L.BY), 256), 256, 0, s>>>(A, L.AX, L.BY, B, g->wa, gf,
-                                                                                  L.I);
-        if constexpr (D == 3)
-            k_recon_z<P, T><<<nblocks(recon_z_threads<P>(L.R), 256), 256, 0, s>>>(B, L.BY, L.R, W, g->wa, gf, L.I);
+        enqueue_recon<D, P, T>(g, Uc, A, B, W, gf);
     }
     {
         StageMark m(g, 2);
@@ -428,13 +453,7 @@ int enqueue_rk(hog_grid* g, double dt_user)
             }
             {
                 StageMark m(g, 1);
-                k_recon_x<D, P, double><<<nblocks(box_size(L.AX), 256), 256, 0, s>>>(src, L.pad, L.AX, A, g->wa,
-                                                                                     nullptr, L.I);
-                k_recon_y<D, P, double><<<nblocks(recon_y_threads<D, P>(L.BY), 256), 256, 0, s>>>(
-                    A, L.AX, L.BY, B, g->wa, nullptr, L.I);
-                if constexpr (D == 3)
-                    k_recon_z<P, double><<<nblocks(recon_z_threads<P>(L.R), 256), 256, 0, s>>>(B, L.BY, L.R, W, g->wa,
-                                                                                               nullptr, L.I);
+                enqueue_recon<D, P, double>(g, src, A, B, W, nullptr);
             }
             {
                 StageMark m(g, 2);
@@ -1015,11 +1034,11 @@ int hog_gate_eval(hog_grid* g, float* logits, unsigned char* flags)
     const long long N = box_size(L.I);
     enqueue_ghost(g);
     if (L.nd == 3)
-        k_gate_infer<3><<<nblocks(N, 16), 64, 0, g->stream>>>(g->U[g->cur], L.pad, L.I,
+        k_gate_infer<3><<<gate_blocks(N, g->cus), 64 * kGateWaves, 0, g->stream>>>(g->U[g->cur], L.pad, L.I,
                                                                static_cast<const GateParams<3>*>(g->gate), g->flags,
                                                                g->logits);
     else
-        k_gate_infer<2><<<nblocks(N, 16), 64, 0, g->stream>>>(g->U[g->cur], L.pad, L.I,
+        k_gate_infer<2><<<gate_blocks(N, g->cus), 64 * kGateWaves, 0, g->stream>>>(g->U[g->cur], L.pad, L.I,
                                                                static_cast<const GateParams<2>*>(g->gate), g->flags,
                                                                g->logits);
     int rc = launch_check("gate");
@@ -1069,24 +1088,46 @@ int hog_harvest(hog_grid* g, const long long* zones, long long n, float* feature
 // Gate training
 // ------------------------------------------------------------------------
 struct hog_mlp {
-    int nf, batch_max, np, t;
+    int nf, batch_max, np, t, nbmax;
     hipStream_t stream;
-    float *prm, *m, *v, *grad, *xb, *h1, *h2, *d1, *d2, *dz, *loss, *logit, *lsum;
+    float *prm, *m, *v, *grad, *lsum, *partial;
+    MlpBatch bt;
 };
 
-static size_t mlp_floats(int nf, int batch_max, int np)
-{
-    return 4 * (size_t)np + (size_t)batch_max * (nf + 4 * kHidden + 3) + 64;
-}
-
 static int mlp_nparam(int nf) { return kHidden * nf + kHidden + kHidden * kHidden + kHidden + kHidden + 1; }
+static int mlp_nb(int n) { return (n + 255) / 256 * 256; }
+
+// Workspace: FP32 parameters, Adam moments and gradient; the per-batch BF16
+// arrays (transposed, [row][sample]) and FP32 per-sample values; the partial
+// gradient tiles of each 256-sample chunk.
+static size_t mlp_bytes(int nf, int batch_max, int np, size_t off[12])
+{
+    const int nb = mlp_nb(batch_max);
+    const int nfp = (nf + 15) / 16 * 16;
+    const int ntile = 4 * (nfp / 16) + 16;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    off[0] = take(sizeof(float) * np);                       // prm
+    off[1] = take(sizeof(float) * np);                       // m
+    off[2] = take(sizeof(float) * np);                       // v
+    off[3] = take(sizeof(float) * np);                       // grad
+    off[4] = take(sizeof(uint16_t) * (size_t)nfp * nb);      // XT
+    off[5] = take(sizeof(uint16_t) * (size_t)kHidden * nb);  // H1T
+    off[6] = take(sizeof(uint16_t) * (size_t)kHidden * nb);  // H2T
+    off[7] = take(sizeof(uint16_t) * 2 * (size_t)kHidden * nb);   // D1T (hi, lo)
+    off[8] = take(sizeof(uint16_t) * 2 * (size_t)kHidden * nb);   // D2T (hi, lo)
+    off[9] = take(sizeof(float) * 3 * (size_t)nb + 64);      // dz, loss, logit, loss sum
+    off[10] = take(sizeof(float) * (size_t)(nb / 256) * ntile * 256);   // partial tiles
+    return o;
+}
 
 extern "C" {
 
 int hog_mlp_workspace_size(int nf, int batch_max, size_t* bytes)
 {
     if ((nf != 36 && nf != 65) || batch_max < 1 || !bytes) return fail(HOG_EINVAL, "nf must be 36 or 65");
-    *bytes = sizeof(float) * mlp_floats(nf, batch_max, mlp_nparam(nf));
+    size_t off[12];
+    *bytes = mlp_bytes(nf, batch_max, mlp_nparam(nf), off);
     return HOG_OK;
 }
 
@@ -1096,25 +1137,32 @@ int hog_mlp_create(int nf, int batch_max, void* ws, size_t bytes, void* stream, 
     int rc = hog_mlp_workspace_size(nf, batch_max, &need);
     if (rc) return rc;
     if (!ws || !out) return fail(HOG_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(HOG_EINVAL, "workspace must be 256-byte aligned");
     if (bytes < need) return fail(HOG_ENOMEM, "workspace too small: %zu < %zu", bytes, need);
     hog_mlp* m = new (std::nothrow) hog_mlp();
     if (!m) return fail(HOG_ENOMEM, "host allocation failed");
     m->nf = nf; m->batch_max = batch_max; m->np = mlp_nparam(nf); m->t = 0;
+    m->nbmax = mlp_nb(batch_max);
     m->stream = static_cast<hipStream_t>(stream);
-    float* f = static_cast<float*>(ws);
-    m->prm = f; f += m->np;
-    m->m = f; f += m->np;
-    m->v = f; f += m->np;
-    m->grad = f; f += m->np;
-    m->xb = f; f += (size_t)batch_max * nf;
-    m->h1 = f; f += (size_t)batch_max * kHidden;
-    m->h2 = f; f += (size_t)batch_max * kHidden;
-    m->d1 = f; f += (size_t)batch_max * kHidden;
-    m->d2 = f; f += (size_t)batch_max * kHidden;
-    m->dz = f; f += batch_max;
-    m->loss = f; f += batch_max;
-    m->logit = f; f += batch_max;
-    m->lsum = f;
+    size_t off[12];
+    mlp_bytes(nf, batch_max, m->np, off);
+    char* w = static_cast<char*>(ws);
+    m->prm = reinterpret_cast<float*>(w + off[0]);
+    m->m = reinterpret_cast<float*>(w + off[1]);
+    m->v = reinterpret_cast<float*>(w + off[2]);
+    m->grad = reinterpret_cast<float*>(w + off[3]);
+    m->bt.XT = reinterpret_cast<uint16_t*>(w + off[4]);
+    m->bt.H1T = reinterpret_cast<uint16_t*>(w + off[5]);
+    m->bt.H2T = reinterpret_cast<uint16_t*>(w + off[6]);
+    m->bt.D1T = reinterpret_cast<uint16_t*>(w + off[7]);
+    m->bt.D2T = reinterpret_cast<uint16_t*>(w + off[8]);
+    float* f = reinterpret_cast<float*>(w + off[9]);
+    m->bt.dz = f;
+    m->bt.loss = f + m->nbmax;
+    m->bt.logit = f + 2 * (size_t)m->nbmax;
+    m->lsum = f + 3 * (size_t)m->nbmax;
+    m->partial = reinterpret_cast<float*>(w + off[10]);
+    m->bt.nb = m->nbmax;
     HIP_TRY(hipMemsetAsync(ws, 0, need, m->stream));
     *out = m;
     return HOG_OK;
@@ -1148,18 +1196,21 @@ int hog_mlp_get_params(hog_mlp* m, float* params)
 static int mlp_backward(hog_mlp* m, const float* X, const float* y, const float* w, int n)
 {
     if (n < 1 || n > m->batch_max || !X || !y) return fail(HOG_EINVAL, "batch must be 1..%d", m->batch_max);
+    MlpBatch bt = m->bt;
+    bt.nb = mlp_nb(n);
+    const int nchunk = bt.nb / 256;
     if (m->nf == 65) {
-        k_mlp_fwd_bwd<65><<<nblocks(n, 128), 128, 0, m->stream>>>(X, y, w, n, m->prm, m->xb, m->h1, m->h2, m->d1,
-                                                                  m->d2, m->dz, m->loss, m->logit);
-        k_mlp_wgrad<65><<<nblocks(m->np, 256), 256, 0, m->stream>>>(m->xb, m->h1, m->h2, m->d1, m->d2, m->dz, n,
-                                                                    m->grad);
+        using S = MlpShape<65>;
+        k_mlp_fwd_bwd<65><<<bt.nb / 64, 64, 0, m->stream>>>(X, y, w, n, m->prm, bt, nullptr);
+        k_mlp_wgrad<65><<<dim3(S::NTILE, nchunk), 64, 0, m->stream>>>(bt, m->partial);
+        k_mlp_reduce<65><<<(S::NTILE * 256 + 63) / 64 + 193, 64, 0, m->stream>>>(bt, m->partial, nchunk, m->grad);
     } else {
-        k_mlp_fwd_bwd<36><<<nblocks(n, 128), 128, 0, m->stream>>>(X, y, w, n, m->prm, m->xb, m->h1, m->h2, m->d1,
-                                                                  m->d2, m->dz, m->loss, m->logit);
-        k_mlp_wgrad<36><<<nblocks(m->np, 256), 256, 0, m->stream>>>(m->xb, m->h1, m->h2, m->d1, m->d2, m->dz, n,
-                                                                    m->grad);
+        using S = MlpShape<36>;
+        k_mlp_fwd_bwd<36><<<bt.nb / 64, 64, 0, m->stream>>>(X, y, w, n, m->prm, bt, nullptr);
+        k_mlp_wgrad<36><<<dim3(S::NTILE, nchunk), 64, 0, m->stream>>>(bt, m->partial);
+        k_mlp_reduce<36><<<(S::NTILE * 256 + 63) / 64 + 193, 64, 0, m->stream>>>(bt, m->partial, nchunk, m->grad);
     }
-    k_sum_fixed<<<1, 256, 0, m->stream>>>(m->loss, n, m->lsum);
+    k_sum_fixed<<<1, 256, 0, m->stream>>>(bt.loss, n, m->lsum);
     return launch_check("mlp backward");
 }
 
@@ -1199,14 +1250,14 @@ int hog_mlp_predict(hog_mlp* m, const float* X, int n, float* logits)
     if (!m || !X || !logits || n < 1) return fail(HOG_EINVAL, "bad arguments");
     for (int s0 = 0; s0 < n; s0 += m->batch_max) {
         const int b = (n - s0 < m->batch_max) ? n - s0 : m->batch_max;
+        MlpBatch bt = m->bt;
+        bt.nb = mlp_nb(b);
         if (m->nf == 65)
-            k_mlp_fwd_bwd<65><<<nblocks(b, 128), 128, 0, m->stream>>>(X + (size_t)s0 * 65, nullptr, nullptr, b, m->prm,
-                                                                      nullptr, nullptr, nullptr, nullptr, nullptr,
-                                                                      nullptr, nullptr, logits + s0);
+            k_mlp_fwd_bwd<65><<<bt.nb / 64, 64, 0, m->stream>>>(X + (size_t)s0 * 65, nullptr, nullptr, b, m->prm, bt,
+                                                              logits + s0);
         else
-            k_mlp_fwd_bwd<36><<<nblocks(b, 128), 128, 0, m->stream>>>(X + (size_t)s0 * 36, nullptr, nullptr, b, m->prm,
-                                                                      nullptr, nullptr, nullptr, nullptr, nullptr,
-                                                                      nullptr, nullptr, logits + s0);
+            k_mlp_fwd_bwd<36><<<bt.nb / 64, 64, 0, m->stream>>>(X + (size_t)s0 * 36, nullptr, nullptr, b, m->prm, bt,
+                                                              logits + s0);
     }
     return launch_check("mlp predict");
 }

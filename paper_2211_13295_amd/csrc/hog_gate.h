@@ -51,8 +51,9 @@ __device__ __forceinline__ float bfround(float x) { return bf2f(f2bf(x)); }
 // Features of variable v of zone (i,j,k) from the padded state: the 13-zone
 // cross (centre, x-2, x-1, x+1, x+2, y-2, ..., z+2; 9 zones in 2D), centred on
 // the zone value and scaled by (max - min + 1e-12 max(1, |centre|)), in FP64,
-// then FP32.
-template <int D>
+// then FP32.  RCP: multiply by the reciprocal of the scale instead of dividing
+// (inference; the harvest keeps the division of the definition).
+template <int D, bool RCP = false>
 __device__ __forceinline__ void gate_features_var(const double* __restrict__ U, const Pad& p, int i, int j, int k,
                                                   int v, float* f)
 {
@@ -73,8 +74,14 @@ __device__ __forceinline__ void gate_features_var(const double* __restrict__ U, 
 #pragma unroll
     for (int s = 1; s < G::NC; ++s) { mx = fmax(mx, val[s]); mn = fmin(mn, val[s]); }
     const double scale = mx - mn + 1e-12 * fmax(1.0, fabs(val[0]));
+    if constexpr (RCP) {
+        const double r = 1.0 / scale;
 #pragma unroll
-    for (int s = 0; s < G::NC; ++s) f[s] = (float)((val[s] - val[0]) / scale);
+        for (int s = 0; s < G::NC; ++s) f[s] = (float)((val[s] - val[0]) * r);
+    } else {
+#pragma unroll
+        for (int s = 0; s < G::NC; ++s) f[s] = (float)((val[s] - val[0]) / scale);
+    }
 }
 
 // All features of zone (i,j,k), ordered [variable][cross].
@@ -90,102 +97,173 @@ __device__ __forceinline__ void gate_features(const double* __restrict__ U, cons
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// One wavefront evaluates the gate on 16 interior zones with BF16 MFMA
-// (16x16x16, FP32 accumulation).  Operand layout of the 16x16x16 BF16 MFMA
-// on CDNA: A lane l holds A[l%16][4(l/16)+0..3], B lane l holds
+// Gate inference.  Each wavefront keeps the BF16 weights as MFMA operand
+// fragments in registers (loaded once) and loops over tiles of 64 interior
+// zones: lane l computes the features of zone l of the tile, one variable per
+// round, into an LDS row of the tile; then per 16-zone slice two BF16 MFMA
+// layers (16x16x16, FP32 accumulation) with the hidden activations written
+// back over the slice's feature rows, and the last layer as per-lane partial
+// dot products summed over the 16 lanes that share a row.  Operand layout of
+// the 16x16x16 BF16 MFMA: A lane l holds A[l%16][4(l/16)+0..3], B lane l holds
 // B[4(l/16)+0..3][l%16], the result lane l holds D[4(l/16)+0..3][l%16].
+constexpr int kGateWaves = 4;   // wavefronts per workgroup
+constexpr int kGateTile = 64;   // zones per wavefront and tile
+
 template <int D>
-__global__ __launch_bounds__(64) void k_gate_infer(const double* __restrict__ U, Pad p, Box I,
-                                                   const GateParams<D>* __restrict__ gp,
-                                                   unsigned char* __restrict__ flags, float* __restrict__ logits)
+struct GateLds {
+    static constexpr int W = GateShape<D>::NFP > kHidden ? GateShape<D>::NFP : kHidden;
+    static constexpr int RS = (W + 4 + 3) / 4 * 4;   // row stride (shorts): 8-byte aligned rows, padded
+};
+
+template <int D>
+__global__ __launch_bounds__(64 * kGateWaves) void k_gate_infer(const double* __restrict__ U, Pad p, Box I,
+                                                                const GateParams<D>* __restrict__ gp,
+                                                                unsigned char* __restrict__ flags,
+                                                                float* __restrict__ logits)
 {
     using G = GateShape<D>;
-    __shared__ uint16_t sx[16][G::NFP];
-    __shared__ float sh[16][kHidden + 1];
+    constexpr int KC = G::NFP / 16;
+    constexpr int RS = GateLds<D>::RS;
+    static_assert(RS >= kHidden && RS % 4 == 0, "rows hold the features, then the hidden activations");
+    __shared__ __align__(16) uint16_t sx[kGateWaves][kGateTile][RS];
     const long long N = box_size(I);
-    const int lane = threadIdx.x;
-    const long long z0 = (long long)blockIdx.x * 16;
-    // features: one (zone, variable) per lane and round
-    for (int t = lane; t < 16 * G::NV; t += 64) {
-        const int zl = t & 15, v = t >> 4;
-        const long long z = z0 + zl;
-        float f[G::NC];
-        if (z < N) {
-            int i, j, k;
-            box_ijk(I, z, i, j, k);
-            gate_features_var<D>(U, p, i, j, k, v, f);
-        } else {
-#pragma unroll
-            for (int q = 0; q < G::NC; ++q) f[q] = 0.0f;
-        }
-#pragma unroll
-        for (int q = 0; q < G::NC; ++q) sx[zl][v * G::NC + q] = f2bf(f[q]);
-    }
-    for (int t = lane; t < 16 * (G::NFP - G::NF); t += 64)
-        sx[t / (G::NFP - G::NF)][G::NF + t % (G::NFP - G::NF)] = (uint16_t)0;
-    __syncthreads();
+    const long long ntiles = (N + kGateTile - 1) / kGateTile;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, g4 = lane >> 4;
-    // layer 1: [16 x NFP] x [NFP x 64]
-    f32x4 acc[4];
+    uint16_t(*row)[RS] = sx[wv];
+
+    // weights as B fragments, biases and the last layer's weights of this lane's columns
+    bf16x4 w1[KC][4], w2[4][4];
+    float b1[4], b2[4], w3[4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int nt = 0; nt < 4; ++nt) {
+        const int col = 16 * nt + r;
 #pragma unroll
-    for (int kc = 0; kc < G::NFP / 16; ++kc) {
-        bf16x4 a;
+        for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = (short)sx[r][16 * kc + 4 * g4 + q];
+            for (int q = 0; q < 4; ++q) w1[kc][nt][q] = (short)gp->W1[col][16 * kc + 4 * g4 + q];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            bf16x4 b;
+        for (int kc = 0; kc < 4; ++kc)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) b[q] = (short)gp->W1[16 * nt + r][16 * kc + 4 * g4 + q];
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
-        }
+            for (int q = 0; q < 4; ++q) w2[kc][nt][q] = (short)gp->W2[col][16 * kc + 4 * g4 + q];
+        b1[nt] = gp->b1[col];
+        b2[nt] = gp->b2[col];
+        w3[nt] = bf2f(gp->w3[col]);
     }
+    const float b3 = gp->b3, thr = gp->logit_thr;
+
+    for (long long t = (long long)blockIdx.x * kGateWaves + wv; t < ntiles; t += (long long)gridDim.x * kGateWaves) {
+        const long long z = t * kGateTile + lane;
+        int i = 0, j = 0, k = 0;
+        const bool live = z < N;
+        if (live) box_ijk(I, z, i, j, k);
+        // features of zone `lane`, variable by variable; the cross of the next
+        // variable is loaded while the current one is scaled (two buffers)
+        const long long c0 = live ? pad_index(p, i, j, k) : pad_index(p, 0, 0, 0);
+        const long long st[3] = {1, p.np[0], (long long)p.np[0] * p.np[1]};
+        double val[2][G::NC];
+        auto load_cross = [&](int v, double* out) {
+            const double* u = U + v * p.vs + c0;
+            out[0] = u[0];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+            for (int ax = 0; ax < D; ++ax) {
+                out[1 + 4 * ax + 0] = u[-2 * st[ax]];
+                out[1 + 4 * ax + 1] = u[-1 * st[ax]];
+                out[1 + 4 * ax + 2] = u[1 * st[ax]];
+                out[1 + 4 * ax + 3] = u[2 * st[ax]];
+            }
+        };
+        load_cross(0, val[0]);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int col = 16 * nt + r;
-            sh[4 * g4 + q][col] = bfround(fmaxf(acc[nt][q] + gp->b1[col], 0.0f));
+        for (int v = 0; v < G::NV; ++v) {
+            if (v + 1 < G::NV) load_cross(v + 1, val[(v + 1) & 1]);
+            const double* x = val[v & 1];
+            double mx = x[0], mn = x[0];
+#pragma unroll
+            for (int q = 1; q < G::NC; ++q) { mx = fmax(mx, x[q]); mn = fmin(mn, x[q]); }
+            const double rs = 1.0 / (mx - mn + 1e-12 * fmax(1.0, fabs(x[0])));
+#pragma unroll
+            for (int q = 0; q < G::NC; ++q)
+                row[lane][v * G::NC + q] = live ? f2bf((float)((x[q] - x[0]) * rs)) : (uint16_t)0;
         }
-    __syncthreads();
-    // layer 2: [16 x 64] x [64 x 64]
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int q = G::NF; q < G::NFP; ++q) row[lane][q] = (uint16_t)0;
+        __builtin_amdgcn_s_waitcnt(0xc07f);       // lgkmcnt(0): this wavefront's rows are written
+        __builtin_amdgcn_wave_barrier();
+        for (int ms = 0; ms < kGateTile / 16; ++ms) {
+            uint16_t(*rs)[RS] = row + 16 * ms;
+            // layer 1: [16 x NFP] x [NFP x 64]
+            f32x4 acc[4];
 #pragma unroll
-    for (int kc = 0; kc < 4; ++kc) {
-        bf16x4 a;
+            for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = (short)f2bf(sh[r][16 * kc + 4 * g4 + q]);
+            for (int kc = 0; kc < KC; ++kc) {
+                bf16x4 a;
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            bf16x4 b;
+                for (int q = 0; q < 4; ++q) a[q] = (short)rs[r][16 * kc + 4 * g4 + q];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) b[q] = (short)gp->W2[16 * nt + r][16 * kc + 4 * g4 + q];
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w1[kc][nt], acc[nt], 0, 0, 0);
+            }
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_wave_barrier();
+            // hidden layer 1 over the slice's feature rows (all reads of them are done)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) rs[4 * g4 + q][16 * nt + r] = f2bf(fmaxf(acc[nt][q] + b1[nt], 0.0f));
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_wave_barrier();
+            // layer 2: [16 x 64] x [64 x 64]
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+                bf16x4 a;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[q] = (short)rs[r][16 * kc + 4 * g4 + q];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w2[kc][nt], acc[nt], 0, 0, 0);
+            }
+            // layer 3: this lane's columns of rows 4 g4 + q, summed over the 16 lanes of the row group
+            float part[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float sum = 0.0f;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) sum += bfround(fmaxf(acc[nt][q] + b2[nt], 0.0f)) * w3[nt];
+                part[q] = sum;
+            }
+#pragma unroll
+            for (int m = 1; m < 16; m <<= 1)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) part[q] += __shfl_xor(part[q], m, 16);
+            if (r < 4) {
+                const long long zz = t * kGateTile + 16 * ms + 4 * g4 + r;
+                float s = b3;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (q == r) s += part[q];
+                if (zz < N) {
+                    if (flags) flags[zz] = s >= thr ? 1 : 0;
+                    if (logits) logits[zz] = s;
+                }
+            }
         }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int col = 16 * nt + r;
-            sh[4 * g4 + q][col] = bfround(fmaxf(acc[nt][q] + gp->b2[col], 0.0f));
-        }
-    __syncthreads();
-    // layer 3 on the VALU
-    if (lane < 16) {
-        const long long z = z0 + lane;
-        float s = gp->b3;
-#pragma unroll
-        for (int q = 0; q < kHidden; ++q) s += sh[lane][q] * bf2f(gp->w3[q]);
-        if (z < N) {
-            if (flags) flags[z] = s >= gp->logit_thr ? 1 : 0;
-            if (logits) logits[z] = s;
-        }
-    }
+}
+
+// Workgroups of the inference kernel: enough tiles per wavefront to amortise
+// the weight loads, at most a few resident rounds of the device.
+inline unsigned gate_blocks(long long nzones, int cus)
+{
+    const long long tiles = (nzones + kGateTile - 1) / kGateTile;
+    const long long want = (tiles + kGateWaves - 1) / kGateWaves;
+    const long long cap = (long long)cus * 4;
+    return (unsigned)(want < cap ? (want > 0 ? want : 1) : cap);
 }
 
 // Largest |omega_k / gamma_k - 1| of the nonlinear weights of one 1D WENO
@@ -296,91 +374,301 @@ struct MlpOffsets {
     static constexpr int N = B3 + 1;
 };
 
-// Per sample: forward, loss term and the backward pass down to dh1; stores
-// the values the weight gradients need, feature-major ([feature][sample]).
+// Training on the matrix cores.  Layout of the per-batch arrays (nb = the
+// batch rounded up to whole 256-sample chunks; samples past the batch carry
+// zero gradients): BF16 arrays transposed, [row][sample], so that an MFMA
+// operand fragment (four consecutive samples of one row) is one 8-byte load:
+//   XT [NFP][nb] the BF16 inputs, H1T, H2T [64][nb] the BF16 hidden layers,
+//   D1T, D2T [2][64][nb] the backward signals of the two hidden layers as
+//   BF16 pairs hi + lo (hi = bf16(d), lo = bf16(d - hi): about 16 bits of
+//   the FP32 value), dz [nb] the output signal, loss and logit [nb].
+struct MlpBatch {
+    uint16_t *XT, *H1T, *H2T, *D1T, *D2T;
+    float *dz, *loss, *logit;
+    int nb;
+};
+
 template <int NF>
-__global__ __launch_bounds__(128) void k_mlp_fwd_bwd(const float* __restrict__ X, const float* __restrict__ y,
-                                                     const float* __restrict__ cw, int n,
-                                                     const float* __restrict__ prm, float* __restrict__ xb,
-                                                     float* __restrict__ h1o, float* __restrict__ h2o,
-                                                     float* __restrict__ d1o, float* __restrict__ d2o,
-                                                     float* __restrict__ dzo, float* __restrict__ losso,
-                                                     float* __restrict__ logito)
+struct MlpShape {
+    static constexpr int NFP = (NF + 15) / 16 * 16;
+    static constexpr int KC = NFP / 16;
+    static constexpr int RS = (NFP > 2 * kHidden ? NFP : 2 * kHidden) + 4;   // row stride (shorts)
+    static constexpr int NT1 = 4 * KC;          // 16x16 tiles of dW1
+    static constexpr int NTILE = NT1 + 16;      // and of dW2
+};
+
+__device__ __forceinline__ void bf16_split(float x, uint16_t& hi, uint16_t& lo)
+{
+    hi = f2bf(x);
+    lo = f2bf(x - bf2f(hi));
+}
+
+// Forward and backward pass of 64 samples per wavefront: per 16-sample slice
+// the two hidden layers (16x16x16 BF16 MFMA, FP32 accumulation, weights as
+// operand fragments in registers), the output and its loss term, the output
+// signal dz = w (sigmoid(logit) - y) / n, d2 = relu'(z2) dz w3, and
+// d1 = relu'(z1) (d2 W2) as two MFMA passes over d2 = hi + lo.  y = NULL:
+// forward only (logits).
+template <int NF>
+__global__ __launch_bounds__(64) void k_mlp_fwd_bwd(const float* __restrict__ X, const float* __restrict__ y,
+                                                    const float* __restrict__ cw, int n,
+                                                    const float* __restrict__ prm, MlpBatch bt,
+                                                    float* __restrict__ logit_out)
 {
     using O = MlpOffsets<NF>;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    float x[NF];
+    using S = MlpShape<NF>;
+    constexpr int KC = S::KC, RS = S::RS;
+    __shared__ __align__(16) uint16_t row[64][RS];
+    const int lane = threadIdx.x, r = lane & 15, g4 = lane >> 4;
+    const int s0 = blockIdx.x * 64;
+    const bool train = y != nullptr;
+    const float inv_n = 1.0f / (float)n;
+
+    bf16x4 w1[KC][4], w2[4][4], w2t[4][4];
+    float b1[4], b2[4], w3[4];
 #pragma unroll
-    for (int q = 0; q < NF; ++q) {
-        x[q] = bfround(X[(long long)s * NF + q]);
-        if (xb) xb[(long long)q * n + s] = x[q];
-    }
-    float z1[kHidden], h1[kHidden];
-    for (int o = 0; o < kHidden; ++o) {
-        float acc = prm[O::B1 + o];
+    for (int nt = 0; nt < 4; ++nt) {
+        const int col = 16 * nt + r;
 #pragma unroll
-        for (int q = 0; q < NF; ++q) acc += bfround(prm[O::W1 + o * NF + q]) * x[q];
-        z1[o] = acc;
-        h1[o] = bfround(fmaxf(acc, 0.0f));
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int f = 16 * kc + 4 * g4 + q;
+                w1[kc][nt][q] = (short)(f < NF ? f2bf(prm[O::W1 + col * NF + f]) : 0);
+            }
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = 16 * kc + 4 * g4 + q;
+                w2[kc][nt][q] = (short)f2bf(prm[O::W2 + col * kHidden + k]);
+                w2t[kc][nt][q] = (short)f2bf(prm[O::W2 + k * kHidden + col]);
+            }
+        b1[nt] = prm[O::B1 + col];
+        b2[nt] = prm[O::B2 + col];
+        w3[nt] = bfround(prm[O::W3 + col]);
     }
-    float z2[kHidden], h2[kHidden];
-    for (int o = 0; o < kHidden; ++o) {
-        float acc = prm[O::B2 + o];
-#pragma unroll 8
-        for (int q = 0; q < kHidden; ++q) acc += bfround(prm[O::W2 + o * kHidden + q]) * h1[q];
-        z2[o] = acc;
-        h2[o] = bfround(fmaxf(acc, 0.0f));
+    const float b3 = prm[O::B3];
+
+    // inputs of this lane's sample, rounded to BF16 (zero past the batch)
+    {
+        const int s = s0 + lane;
+#pragma unroll 4
+        for (int f = 0; f < S::NFP; ++f) {
+            const uint16_t x = (s < n && f < NF) ? f2bf(X[(long long)s * NF + f]) : (uint16_t)0;
+            row[lane][f] = x;
+            if (train) bt.XT[(long long)f * bt.nb + s] = x;
+        }
     }
-    float logit = prm[O::B3];
-    for (int q = 0; q < kHidden; ++q) logit += bfround(prm[O::W3 + q]) * h2[q];
-    if (logito) logito[s] = logit;
-    if (!y) return;
-    const float yy = y[s], c = cw ? cw[s] : 1.0f;
-    const float pr = 1.0f / (1.0f + expf(-logit));
-    losso[s] = c * (fmaxf(logit, 0.0f) - logit * yy + log1pf(expf(-fabsf(logit))));
-    const float dz = c * (pr - yy) / (float)n;
-    dzo[s] = dz;
-    float d2[kHidden];
-    for (int o = 0; o < kHidden; ++o) {
-        d2[o] = z2[o] > 0.0f ? dz * bfround(prm[O::W3 + o]) : 0.0f;
-        d2o[(long long)o * n + s] = d2[o];
-        h1o[(long long)o * n + s] = h1[o];
-        h2o[(long long)o * n + s] = h2[o];
-    }
-    for (int q = 0; q < kHidden; ++q) {
-        float acc = 0.0f;
-#pragma unroll 8
-        for (int o = 0; o < kHidden; ++o) acc += d2[o] * bfround(prm[O::W2 + o * kHidden + q]);
-        d1o[(long long)q * n + s] = z1[q] > 0.0f ? acc : 0.0f;
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    for (int ms = 0; ms < 4; ++ms) {
+        uint16_t(*rs)[RS] = row + 16 * ms;
+        const int sr = s0 + 16 * ms + 4 * g4;          // first sample of this lane's result rows
+        // layer 1
+        f32x4 z1[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) z1[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            bf16x4 a;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = (short)rs[r][16 * kc + 4 * g4 + q];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) z1[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w1[kc][nt], z1[nt], 0, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                z1[nt][q] += b1[nt];
+                const uint16_t h = f2bf(fmaxf(z1[nt][q], 0.0f));
+                rs[4 * g4 + q][16 * nt + r] = h;
+                if (train) bt.H1T[(long long)(16 * nt + r) * bt.nb + sr + q] = h;
+            }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        // layer 2
+        f32x4 z2[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) z2[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+            bf16x4 a;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = (short)rs[r][16 * kc + 4 * g4 + q];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) z2[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w2[kc][nt], z2[nt], 0, 0, 0);
+        }
+        // output: partial dot products over this lane's columns, summed over the 16 lanes of the row group
+        float part[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float sum = 0.0f;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                z2[nt][q] += b2[nt];
+                const uint16_t h = f2bf(fmaxf(z2[nt][q], 0.0f));
+                if (train) bt.H2T[(long long)(16 * nt + r) * bt.nb + sr + q] = h;
+                sum += bf2f(h) * w3[nt];
+            }
+            part[q] = sum;
+        }
+#pragma unroll
+        for (int m = 1; m < 16; m <<= 1)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) part[q] += __shfl_xor(part[q], m, 16);
+        float dz[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int s = sr + q;
+            const float lg = b3 + part[q];
+            dz[q] = 0.0f;
+            if (s < n) {
+                if (r == q) {
+                    if (logit_out) logit_out[s] = lg;
+                    if (train) bt.logit[s] = lg;
+                }
+                if (train) {
+                    const float yy = y[s], c = cw ? cw[s] : 1.0f;
+                    const float pr = 1.0f / (1.0f + expf(-lg));
+                    dz[q] = c * (pr - yy) * inv_n;
+                    if (r == q) bt.loss[s] = c * (fmaxf(lg, 0.0f) - lg * yy + log1pf(expf(-fabsf(lg))));
+                }
+            } else if (train && r == q) {
+                bt.loss[s] = 0.0f;
+            }
+            if (train && r == q) bt.dz[s] = dz[q];
+        }
+        if (!train) continue;
+        // d2 = relu'(z2) dz w3, written as hi / lo rows (columns 0..63 / 64..127) and transposed to memory
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float d2 = z2[nt][q] > 0.0f ? dz[q] * w3[nt] : 0.0f;
+                uint16_t hi, lo;
+                bf16_split(d2, hi, lo);
+                const int col = 16 * nt + r;
+                rs[4 * g4 + q][col] = hi;
+                rs[4 * g4 + q][kHidden + col] = lo;
+                bt.D2T[(long long)col * bt.nb + sr + q] = hi;
+                bt.D2T[((long long)kHidden + col) * bt.nb + sr + q] = lo;
+            }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        // d1 = relu'(z1) (d2 W2)
+        f32x4 d1[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) d1[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int part2 = 0; part2 < 2; ++part2)
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+                bf16x4 a;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[q] = (short)rs[r][part2 * kHidden + 16 * kc + 4 * g4 + q];
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    d1[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w2t[kc][nt], d1[nt], 0, 0, 0);
+            }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float d = z1[nt][q] > 0.0f ? d1[nt][q] : 0.0f;
+                uint16_t hi, lo;
+                bf16_split(d, hi, lo);
+                const int col = 16 * nt + r;
+                bt.D1T[(long long)col * bt.nb + sr + q] = hi;
+                bt.D1T[((long long)kHidden + col) * bt.nb + sr + q] = lo;
+            }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Weight gradients: one thread per parameter, sum over the batch in sample
-// order (deterministic).
+// Weight gradients as MFMA tiles: one wavefront per (16x16 output tile,
+// chunk of 256 samples) sums dW1 = d1^T x or dW2 = d2^T h1 over its chunk
+// (two passes, d = hi + lo) and stores the partial tile; k_mlp_reduce adds
+// the chunks in order.
 template <int NF>
-__global__ __launch_bounds__(256) void k_mlp_wgrad(const float* __restrict__ xb, const float* __restrict__ h1,
-                                                   const float* __restrict__ h2, const float* __restrict__ d1,
-                                                   const float* __restrict__ d2, const float* __restrict__ dz,
-                                                   int n, float* __restrict__ grad)
+__global__ __launch_bounds__(64) void k_mlp_wgrad(MlpBatch bt, float* __restrict__ partial)
+{
+    using S = MlpShape<NF>;
+    const int lane = threadIdx.x, r = lane & 15, g4 = lane >> 4;
+    const int tl = blockIdx.x, ch = blockIdx.y;
+    int mt, ntl;
+    const uint16_t *A, *Bm;
+    if (tl < S::NT1) { mt = tl / S::KC; ntl = tl % S::KC; A = bt.D1T; Bm = bt.XT; }
+    else { mt = (tl - S::NT1) / 4; ntl = (tl - S::NT1) % 4; A = bt.D2T; Bm = bt.H1T; }
+    const long long nb = bt.nb;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    const long long c0 = (long long)ch * 256;
+#pragma unroll 4
+    for (int ks = 0; ks < 16; ++ks) {
+        const long long s = c0 + 16 * ks + 4 * g4;
+        const bf16x4 b = *reinterpret_cast<const bf16x4*>(Bm + (long long)(16 * ntl + r) * nb + s);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bf16x4 a = *reinterpret_cast<const bf16x4*>(A + ((long long)h * kHidden + 16 * mt + r) * nb + s);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        }
+    }
+    float* out = partial + ((long long)ch * S::NTILE + tl) * 256;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[(4 * g4 + q) * 16 + r] = acc[q];
+}
+
+// Gradient vector: the weight tiles summed over the chunks in order, the
+// biases and the output weights by one wavefront per parameter row (lanes
+// take every 64th sample, then a fixed-order tree over the lanes).
+template <int NF>
+__global__ __launch_bounds__(64) void k_mlp_reduce(MlpBatch bt, const float* __restrict__ partial, int nchunk,
+                                                   float* __restrict__ grad)
 {
     using O = MlpOffsets<NF>;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= O::N) return;
-    const float *a = nullptr, *b = nullptr;
-    if (t < O::B1) { a = d1 + (long long)(t / NF) * n; b = xb + (long long)(t % NF) * n; }
-    else if (t < O::W2) { a = d1 + (long long)(t - O::B1) * n; }
-    else if (t < O::B2) { const int u = t - O::W2; a = d2 + (long long)(u / kHidden) * n; b = h1 + (long long)(u % kHidden) * n; }
-    else if (t < O::W3) { a = d2 + (long long)(t - O::B2) * n; }
-    else if (t < O::B3) { a = dz; b = h2 + (long long)(t - O::W3) * n; }
-    else { a = dz; }
-    float acc = 0.0f;
-    if (b) {
-        for (int s = 0; s < n; ++s) acc += a[s] * b[s];
-    } else {
-        for (int s = 0; s < n; ++s) acc += a[s];
+    using S = MlpShape<NF>;
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x;
+    const int nwt = (S::NTILE * 256 + 63) / 64;      // blocks for the weight tiles
+    if (b < nwt) {
+        const int e = b * 64 + lane;                  // element of the tile set
+        if (e >= S::NTILE * 256) return;
+        const int tl = e / 256, w = e % 256, i = w / 16, j = w % 16;
+        float sum = 0.0f;
+        for (int c = 0; c < nchunk; ++c) sum += partial[((long long)c * S::NTILE + tl) * 256 + w];
+        if (tl < S::NT1) {
+            const int o = 16 * (tl / S::KC) + i, f = 16 * (tl % S::KC) + j;
+            if (f < NF) grad[O::W1 + o * NF + f] = sum;
+        } else {
+            const int t2 = tl - S::NT1;
+            const int o = 16 * (t2 / 4) + i, q = 16 * (t2 % 4) + j;
+            grad[O::W2 + o * kHidden + q] = sum;
+        }
+        return;
     }
-    grad[t] = acc;
+    const int rrow = b - nwt;                          // 0..63 b1, 64..127 b2, 128..191 w3, 192 b3
+    const long long nb = bt.nb;
+    float sum = 0.0f;
+    for (long long s = lane; s < nb; s += 64) {
+        if (rrow < 64) sum += bf2f(bt.D1T[rrow * nb + s]) + bf2f(bt.D1T[(kHidden + rrow) * nb + s]);
+        else if (rrow < 128) sum += bf2f(bt.D2T[(rrow - 64) * nb + s]) + bf2f(bt.D2T[(kHidden + rrow - 64) * nb + s]);
+        else if (rrow < 192) sum += bt.dz[s] * bf2f(bt.H2T[(rrow - 128) * nb + s]);
+        else sum += bt.dz[s];
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) sum += __shfl_xor(sum, m, 64);
+    if (lane == 0) {
+        if (rrow < 64) grad[O::B1 + rrow] = sum;
+        else if (rrow < 128) grad[O::B2 + rrow - 64] = sum;
+        else if (rrow < 192) grad[O::W3 + rrow - 128] = sum;
+        else grad[O::B3] = sum;
+    }
 }
 
 // Adam on the FP32 masters.

@@ -285,12 +285,16 @@ __device__ __forceinline__ void march_line(const T* __restrict__ src, long long 
     double w[5];
 #pragma unroll
     for (int o = 0; o < 5; ++o) w[o] = (double)src[c0 + (o - 2) * stride];
+    // the gate flag of the next zone is loaded with the next stencil value, so
+    // the two loads of a step share one round trip
+    bool gnext = NC >= 1 && gate_at(0);
     long long zi = z0;
     for (int s = 0; s < len; ++s) {
         out0[zi] = (T)w[2];
+        const bool gcur = gnext;
         if constexpr (NC >= 1) {
             WenoArgs wa = wa0;
-            if (gate_at(s)) wa.linear = 1;
+            if (gcur) wa.linear = 1;
             T c[P + 1];
             weno_line<P, T>(w, c, wa);
 #pragma unroll
@@ -300,6 +304,7 @@ __device__ __forceinline__ void march_line(const T* __restrict__ src, long long 
 #pragma unroll
             for (int o = 0; o < 4; ++o) w[o] = w[o + 1];
             w[4] = (double)src[c0 + (long long)(s + 3) * stride];
+            if constexpr (NC >= 1) gnext = gate_at(s + 1);
         }
         zi += zstride;
     }
@@ -1007,6 +1012,10 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 #pragma unroll
                     for (int v = 0; v < NV; ++v) rz[(d * NV + v) * RS + pos[d]] = F[d][v];
             } else {
+                // The iterate of iteration it has time degree it (the first one is
+                // constant in time): in iteration 1 the modes of time degree >= 2
+                // are exactly zero, and their terms are skipped (uniform branches).
+                const bool deg1 = it == 1;
                 T Qe[P][NV];                        // time modes e = 1..P at the node
 #pragma unroll
                 for (int e = 0; e < P; ++e)
@@ -1015,9 +1024,19 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
                 const T* qz = sq + zs * MST * NV;
 #pragma unroll
                 for (int m = MS; m < MST; ++m) {
+                    if (M.e[m] != 1) continue;
                     const T phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) Qe[M.e[m] - 1][v] += qz[m * NV + v] * phi;
+                    for (int v = 0; v < NV; ++v) Qe[0][v] += qz[m * NV + v] * phi;
+                }
+                if (!deg1) {
+#pragma unroll
+                    for (int m = MS; m < MST; ++m) {
+                        if (M.e[m] == 1) continue;
+                        const T phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) Qe[M.e[m] - 1][v] += qz[m * NV + v] * phi;
+                    }
                 }
                 T Racc[NE - 1][D][NV];
                 T Rtop[NV];
@@ -1034,9 +1053,12 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
                     T U[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        T s = Qe[P - 1][v];
+                        T s = Qe[0][v];
+                        if (!deg1) {
+                            s = Qe[P - 1][v];
 #pragma unroll
-                        for (int e = P - 2; e >= 0; --e) s = s * T(RL.t[l]) + Qe[e][v];
+                            for (int e = P - 2; e >= 0; --e) s = s * T(RL.t[l]) + Qe[e][v];
+                        }
                         U[v] = Q0[v] + s * T(RL.t[l]);
                     }
                     T F[D][NV];

@@ -188,13 +188,15 @@ __device__ __forceinline__ void riemann(const T* UL, const T* UR, int dir, int s
         for (int v = 0; v < NV; ++v) F[v] = FL[v];
         return;
     }
-    if (SR <= T(0) && !(Ss >= T(0))) {
+    // in the order S_L >= 0, S* >= 0, S_R > 0, else the right flux (a NaN speed
+    // fails every test and falls through to the right flux)
+    const bool left = Ss >= T(0);
+    if (!left && !(SR > T(0))) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) F[v] = FR[v];
         return;
     }
     // star state on the side the contact leaves behind
-    const bool left = Ss >= T(0);
     const T* Uk = left ? UL : UR;
     const T* Fk = left ? FL : FR;
     const T Sk = left ? SL : SR;

@@ -2,8 +2,8 @@
 
 Data: training samples harvested by the library (hog_harvest) from FP64
 fourth-order runs of the 3D workloads -- the extruded vortex with seeded
-density modes (periodic) and the multi-blast (outflow) -- at several steps of
-each run; label smooth <=> the largest |omega_k/gamma_k - 1| over the
+density modes on 128^3 (periodic) and the multi-blast on 256^3 (outflow) --
+at steps 10, 20, ..., 50 of each run, 1M zones per snapshot; label smooth <=> the largest |omega_k/gamma_k - 1| over the
 variables and the 1D applications centred at the zone is <= 0.25.  The set is
 stratified to equal class counts, split 90/10 (seeded), and the network is
 trained with the library's kernels (hog_mlp_step: Adam, batch 4096, learning
@@ -39,20 +39,21 @@ def he_init(nf, seed):
 
 
 def harvest(hog, torch, problems, order, steps_between, snapshots, per_snapshot, seed, log):
+    """Samples at steps steps_between, 2 steps_between, ... of an FP64 run of
+    each problem (CFL time step computed on the device)."""
     rng = np.random.default_rng(seed)
     feats, devs = [], []
     for pb in problems:
         g = hog.Grid.from_problem(pb, order)
         N = pb.U[0].size
         for s in range(snapshots):
+            g.advance(steps_between)
             zones = np.arange(N) if per_snapshot >= N else np.sort(rng.choice(N, per_snapshot, replace=False))
             F, d = g.harvest(zones)
             feats.append(F)
             devs.append(d)
-            log(f"  harvest {pb.meta.get('name')} n={pb.n[0]} snapshot {s}: {len(zones)} zones, "
+            log(f"  harvest {pb.meta.get('name')} n={pb.n[0]} step {(s + 1) * steps_between}: {len(zones)} zones, "
                 f"smooth fraction {float((d <= 0.25).float().mean()):.3f}")
-            if s + 1 < snapshots:
-                g.advance(steps_between)
         g.close()
         torch.cuda.empty_cache()
     return torch.cat(feats), torch.cat(devs)
@@ -64,6 +65,7 @@ def train(hog, torch, X, y, epochs, lr, batch, seed, log):
     gen = torch.Generator(device="cpu").manual_seed(seed)
     n = X.shape[0]
     steps = max(1, epochs * n // batch)
+    torch.cuda.synchronize()
     t0 = time.time()
     for it in range(steps):
         idx = torch.randint(0, n, (batch,), generator=gen).cuda()
@@ -72,17 +74,18 @@ def train(hog, torch, X, y, epochs, lr, batch, seed, log):
         loss = m.step(X[idx].contiguous(), y[idx].contiguous(), None, lr=lr_t, want_loss=want)
         if want:
             log(f"  step {it}/{steps} loss {loss:.4f} ({time.time() - t0:.1f} s)")
-    return m
+    torch.cuda.synchronize()
+    return m, steps * batch / (time.time() - t0)
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--out", default=os.path.join(HERE, "gate_o4_3d.npz"))
     ap.add_argument("--n-vortex", type=int, default=128)
-    ap.add_argument("--n-blast", type=int, default=128)
+    ap.add_argument("--n-blast", type=int, default=256)
     ap.add_argument("--snapshots", type=int, default=5)
     ap.add_argument("--steps-between", type=int, default=10)
-    ap.add_argument("--per-snapshot", type=int, default=600000)
+    ap.add_argument("--per-snapshot", type=int, default=1000000)
     ap.add_argument("--samples", type=int, default=5000000)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -115,7 +118,7 @@ def main(argv=None):
     ntr = int(0.9 * X.shape[0])
     Xtr, ytr, Xva, yva = X[:ntr], y[:ntr], X[ntr:], y[ntr:]
     log(f"training set {ntr}, held out {X.shape[0] - ntr} (balanced)")
-    m = train(hog, torch, Xtr, ytr, a.epochs, a.lr, a.batch, a.seed, log)
+    m, rate = train(hog, torch, Xtr, ytr, a.epochs, a.lr, a.batch, a.seed, log)
     lv = m.predict(Xva)
     neg_l = lv[yva == 0]
     # smallest logit threshold with false-smooth rate <= target
@@ -130,6 +133,8 @@ def main(argv=None):
     params = m.get_params()
     stats = dict(theta=theta, logit_threshold=thr, heldout_false_smooth_rate=fsr, heldout_smooth_recall=recall,
                  heldout_accuracy_at_half=acc, train_samples=ntr, heldout_samples=int(X.shape[0] - ntr),
+                 harvested=int(dev.numel()), balanced_samples=int(X.shape[0]),
+                 training_samples_per_s=rate,
                  sources=[p.meta.get("name") + f"_{p.n[0]}" for p in probs], snapshots=a.snapshots,
                  steps_between=a.steps_between, epochs=a.epochs, lr=a.lr, batch=a.batch, seed=a.seed)
     np.savez(a.out, params=params, theta=np.array(theta))

@@ -38,7 +38,7 @@ class HogConfig(C.Structure):
         ("ndim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
         ("order", C.c_int), ("riemann", C.c_int), ("bc", C.c_int * 3),
         ("precision", C.c_int), ("linear_weno", C.c_int), ("debug", C.c_int),
-        ("positivity", C.c_int), ("stepper", C.c_int), ("reserved", C.c_int * 2),
+        ("positivity", C.c_int), ("stepper", C.c_int), ("characteristic", C.c_int), ("reserved", C.c_int),
         ("gamma", C.c_double), ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
         ("cfl", C.c_double), ("weno_eps", C.c_double), ("g3", C.c_double * 3), ("g4", C.c_double * 4),
     ]
@@ -54,6 +54,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} not found: build it with `python paper_2211_13295_amd/build.py`")
+    # torch first: it carries its own HIP runtime under the same soname, and
+    # the library must bind to that one so that both share one runtime (and
+    # torch's device memory and streams)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, cp = C.c_void_p, C.POINTER(HogConfig)
     L.hog_abi_version.restype = C.c_int
@@ -119,7 +123,7 @@ def _check(rc):
 
 def make_config(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("periodic",) * 3,
                 linear_weno=False, debug=False, weno_eps=0.0, g3=(0, 0, 0), g4=(0, 0, 0, 0),
-                positivity=True, precision="fp64", stepper="ader"):
+                positivity=True, precision="fp64", stepper="ader", characteristic=False):
     c = HogConfig()
     c.ndim = ndim
     c.nx, c.ny = int(n[0]), int(n[1])
@@ -133,6 +137,7 @@ def make_config(ndim, n, order, h, gamma=1.4, cfl=0.4, riemann="hllc", bc=("peri
     c.debug = int(bool(debug))
     c.positivity = int(bool(positivity))
     c.stepper = STEPPER[stepper] if isinstance(stepper, str) else int(stepper)
+    c.characteristic = int(bool(characteristic))
     c.gamma = gamma
     c.dx, c.dy = h[0], h[1]
     c.dz = h[2] if ndim == 3 else 1.0
@@ -450,9 +455,10 @@ class Mlp:
         L = load()
         nb = C.c_size_t(0)
         _check(L.hog_mlp_workspace_size(nf, batch_max, C.byref(nb)))
-        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+        base = (self.workspace.data_ptr() + 255) // 256 * 256
         h = C.c_void_p()
-        _check(L.hog_mlp_create(nf, batch_max, C.c_void_p(self.workspace.data_ptr()), nb.value,
+        _check(L.hog_mlp_create(nf, batch_max, C.c_void_p(base), nb.value,
                                 C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(h)))
         self._h = h
         self.np = 64 * nf + 64 + 64 * 64 + 64 + 64 + 1

@@ -99,6 +99,7 @@ def test_stepper_external_and_stream_configs_without_a_device():
                       (6, ext)):
         assert L.hog_stream_workspace_size(ctypes.byref(cfg), slab, ctypes.byref(nb)) == hog.HOG_EINVAL
 
+
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libhog.so not built")
 def test_static_step_rejects_grids_beyond_its_array_without_a_device():
     """hog_step_static checks the configuration and its workspace size against

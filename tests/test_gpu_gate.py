@@ -194,6 +194,42 @@ def _run(hog, pb, steps, precision, gate=None):
     return out
 
 
+def test_trained_gate_gain_four_quadrant(hog):
+    """What the network's selection gains on the headline workload, scaled
+    down (four-quadrant Riemann problem, 64^3, fourth order, 20 steps, mixed
+    path): a large share of the zones runs on the linear weights, and the
+    state stays close to the FP64 path -- much closer than with the same share
+    of zones chosen at random each step, or with linear weights everywhere."""
+    z = np.load(GATE_FILE)
+    gate = (z["params"], float(z["theta"]))
+    pb = icgen.four_quadrant(n=64, seed=5)
+    steps = 20
+    ref, _, _ = _run(hog, pb, steps, "fp64")
+    Ug, _, frac = _run(hog, pb, steps, "mixed", gate)
+    rng = np.random.default_rng(9)
+    g = hog.Grid.from_problem(pb, 4, precision="mixed")
+    for _ in range(steps):
+        g.set_gate_flags((rng.uniform(size=pb.U[0].shape) < frac).astype(np.uint8))
+        g.advance(1)
+    Ur = g.get_state()
+    g.set_gate_flags(np.ones(pb.U[0].shape, np.uint8))
+    g.set_state(pb.U)
+    try:
+        g.advance(steps)
+        Ul = g.get_state()
+    except hog.HogError:                 # linear weights at the discontinuities: a non-physical state
+        Ul = np.full_like(ref, np.inf)
+    g.close()
+    Um, _, _ = _run(hog, pb, steps, "mixed")
+    rel = {k: float(np.abs(U - ref).sum() / np.abs(ref).sum()) for k, U in
+           (("gate", Ug), ("random", Ur), ("linear", Ul), ("mixed", Um))}
+    print(f"gate gain, four-quadrant 64^3: {100 * frac:.1f}% of zones on linear weights; rel L1 vs FP64 {rel}",
+          flush=True)
+    assert frac > 0.3
+    assert rel["gate"] <= 1e-3
+    assert rel["random"] >= 5.0 * rel["gate"] and rel["linear"] >= 5.0 * rel["gate"]
+
+
 def test_trained_gate_gain_smooth(hog):
     """What the trained gate buys on smooth flow with a known solution (the
     isentropic vortex extruded along z, 40^3, fourth order, 10 steps): the
@@ -213,6 +249,29 @@ def test_trained_gate_gain_smooth(hog):
           f"{err['gated']:.4e} gated, {err['mixed']:.4e} mixed, {err['fp64']:.4e} FP64", flush=True)
     assert frac > 0.005
     assert err["gated"] <= 1.02 * err["mixed"]
+
+
+def test_trained_gate_keeps_the_vortex_order_3d(hog):
+    """The mixed path with the trained gate keeps the design order on the
+    isentropic vortex extruded along z (fourth order, 32^3 -> 64^3 on
+    [0,10]^3, to t = 1): the density L1 error against the exact translated
+    vortex falls at least as fast as order 3.75, like the ungated mixed path's
+    floor."""
+    z = np.load(GATE_FILE)
+    gate = (z["params"], float(z["theta"]))
+    errs, fracs = [], []
+    for n in (32, 64):
+        pb = icgen.vortex3d_perturbed(n=n, seed=2, amp=0.0)
+        g = hog.Grid.from_problem(pb, 4, precision="mixed")
+        g.set_gate(gate[0], theta=gate[1])
+        fracs.append(float(g.gate_eval()[1].mean()))
+        t = g.advance(100000, t_end=1.0)
+        ex = icgen.vortex_exact_density(n, t)
+        errs.append(float(np.abs(g.get_state()[0] - ex[None]).mean()))
+        g.close()
+    rate = np.log2(errs[0] / errs[1])
+    print(f"mixed + trained gate, 3D vortex: errors {errs}, order {rate:.2f}, gated fractions {fracs}", flush=True)
+    assert rate >= 3.75
 
 
 def test_trained_gate_gain_shocks(hog):

@@ -396,3 +396,23 @@ def test_advance_keeps_the_state_before_a_failing_step(hog, t_end):
     g2.set_state(pb.U)
     assert g2.advance(2) > 0
     np.testing.assert_array_equal(g2.get_state(), states[2])
+
+
+@pytest.mark.parametrize("riemann", ["hllc", "hll", "rusanov"])
+def test_inadmissible_face_states_without_fallback_match_oracle(hog, riemann):
+    """A cold rarefaction at fourth order without the positivity fallback:
+    many face states have negative pressure, so the sound speeds and the
+    Roe-averaged wave speeds are undefined (NaN).  The branches of the
+    solvers are taken in the order the scheme defines (HLLC: S_L >= 0,
+    S* >= 0, S_R > 0, else the right flux; every comparison with NaN is false),
+    so the GPU takes the same branch as the oracle, state for state."""
+    pb = icgen.cold_wave(n=32, ndim=2, amp=2.0, p0=1e-3)
+    c = oracle.cfg_from_problem(pb, 4, positivity=False, riemann=riemann)
+    dt, _ = oracle.cfl_dt(c, pb.U)
+    Uo = oracle.step(c, pb.U, dt)
+    g = grid_for(hog, pb, 4, positivity=False, riemann=riemann)
+    g.step(dt, want_next=False)
+    U = g.get_state()
+    assert np.array_equal(np.isnan(U), np.isnan(Uo))
+    fin = np.isfinite(Uo)
+    np.testing.assert_allclose(U[fin], Uo[fin], rtol=1e-12, atol=1e-13 * np.abs(Uo[fin]).max())

@@ -282,3 +282,21 @@ def test_anti_diffusion_lies_in_the_degenerate_fields(solver):
         assert abs(Linv[0] @ dF) <= 1e-12 * (1 + np.abs(dF).max())
         assert abs(Linv[4] @ dF) <= 1e-12 * (1 + np.abs(dF).max())
         assert np.abs(dF).max() > 1e-6      # and it does change the HLL flux
+
+
+def test_hllc_with_undefined_wave_speeds_falls_through_to_the_right_flux():
+    """Negative pressure on both sides (as in the face states of a cold flow
+    without the positivity fallback) leaves the sound speeds and the Roe sound
+    speed undefined (NaN).  Taken in the defined order S_L >= 0, S* >= 0,
+    S_R > 0, every test fails and HLLC returns the physical flux of the right
+    state; HLL returns NaN (its last branch is the HLL average)."""
+    c2 = oracle.make_cfg(2, (4, 4, 1), 4, (0.1, 0.1, 0.1), riemann="hllc")
+    UL = np.array([0.984452238, 0.378705354, 0.0, 0.0692566391])
+    UR = np.array([0.984446347, 0.378744513, 0.0, 0.0694100894])
+    G = 1.4
+    for U in (UL, UR):
+        assert (G - 1) * (U[3] - 0.5 * U[1] ** 2 / U[0]) < 0
+    F = oracle.riemann(c2, 0, UL, UR)
+    np.testing.assert_array_equal(F, oracle.phys_flux(c2, 0, UR))
+    ch = oracle.make_cfg(2, (4, 4, 1), 4, (0.1, 0.1, 0.1), riemann="hll")
+    assert np.isnan(oracle.riemann(ch, 0, UL, UR)).all()
