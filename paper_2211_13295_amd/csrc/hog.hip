@@ -964,7 +964,8 @@ static int set_gate_t(hog_grid* g, const float* prm, double theta)
     GateParams<D> h;
     std::memset(&h, 0, sizeof h);
     for (int o = 0; o < kHidden; ++o)
-        for (int f = 0; f < G::NF; ++f) h.W1[o][f] = host_bf16(prm[O::W1 + o * G::NF + f]);
+        for (int f = 0; f < G::NF; ++f)   // device feature layout: variable blocks of NCB columns
+            h.W1[o][(f / G::NC) * G::NCB + f % G::NC] = host_bf16(prm[O::W1 + o * G::NF + f]);
     for (int o = 0; o < kHidden; ++o) {
         h.b1[o] = prm[O::B1 + o];
         h.b2[o] = prm[O::B2 + o];

@@ -22,15 +22,21 @@ struct GateShape {
     static constexpr int NV = D + 2;
     static constexpr int NC = 4 * D + 1;          // cross: centre + 4 per axis
     static constexpr int NF = NV * NC;            // 36 (2D) / 65 (3D)
-    static constexpr int NFP = (NF + 15) / 16 * 16;   // padded to the MFMA K step
+    // device layout of the features in inference: each variable's block padded
+    // to an even width (pairs of BF16 features are written as one word)
+    static constexpr int NCB = NC + 1;
+    static constexpr int NFL = NV * NCB;          // 40 (2D) / 70 (3D)
+    static constexpr int NFP = (NFL + 31) / 32 * 32;   // padded to the MFMA K step (32)
     static constexpr int NPARAM = kHidden * NF + kHidden + kHidden * kHidden + kHidden + kHidden + 1;
 };
 
-// Device copy of the gate (BF16 weights, FP32 biases).
+// Device copy of the gate (BF16 weights, FP32 biases).  W1's columns are in
+// the device feature layout (variable v, cross point q at column v NCB + q;
+// the pad columns are zero).
 template <int D>
-struct GateParams {
+struct __align__(16) GateParams {
     using G = GateShape<D>;
-    uint16_t W1[kHidden][G::NFP];   // zero-padded columns
+    uint16_t W1[kHidden][G::NFP];
     float b1[kHidden];
     uint16_t W2[kHidden][kHidden];
     float b2[kHidden];
@@ -39,12 +45,8 @@ struct GateParams {
     float logit_thr;
 };
 
-__device__ __forceinline__ uint16_t f2bf(float x)
-{
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// FP32 -> BF16 with round to nearest even (gfx950's conversion instruction)
+__device__ __forceinline__ uint16_t f2bf(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ __forceinline__ float bfround(float x) { return bf2f(f2bf(x)); }
 
@@ -95,24 +97,26 @@ __device__ __forceinline__ void gate_features(const double* __restrict__ U, cons
 }
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Gate inference.  Each wavefront keeps the BF16 weights as MFMA operand
 // fragments in registers (loaded once) and loops over tiles of 64 interior
 // zones: lane l computes the features of zone l of the tile, one variable per
 // round, into an LDS row of the tile; then per 16-zone slice two BF16 MFMA
-// layers (16x16x16, FP32 accumulation) with the hidden activations written
+// layers (16x16x32, FP32 accumulation) with the hidden activations written
 // back over the slice's feature rows, and the last layer as per-lane partial
 // dot products summed over the 16 lanes that share a row.  Operand layout of
-// the 16x16x16 BF16 MFMA: A lane l holds A[l%16][4(l/16)+0..3], B lane l holds
-// B[4(l/16)+0..3][l%16], the result lane l holds D[4(l/16)+0..3][l%16].
+// gfx950's 16x16x32 BF16 MFMA: A lane l holds A[l%16][8(l/16)+0..7], B lane l
+// holds B[8(l/16)+0..7][l%16], the result lane l holds D[4(l/16)+0..3][l%16].
 constexpr int kGateWaves = 4;   // wavefronts per workgroup
 constexpr int kGateTile = 64;   // zones per wavefront and tile
 
 template <int D>
 struct GateLds {
     static constexpr int W = GateShape<D>::NFP > kHidden ? GateShape<D>::NFP : kHidden;
-    static constexpr int RS = (W + 4 + 3) / 4 * 4;   // row stride (shorts): 8-byte aligned rows, padded
+    static constexpr int RS = W + 8;   // row stride (shorts): 16-byte aligned rows, padded
 };
 
 template <int D>
@@ -122,9 +126,9 @@ __global__ __launch_bounds__(64 * kGateWaves) void k_gate_infer(const double* __
                                                                 float* __restrict__ logits)
 {
     using G = GateShape<D>;
-    constexpr int KC = G::NFP / 16;
+    constexpr int KC = G::NFP / 32;
     constexpr int RS = GateLds<D>::RS;
-    static_assert(RS >= kHidden && RS % 4 == 0, "rows hold the features, then the hidden activations");
+    static_assert(RS >= kHidden && RS % 8 == 0, "rows hold the features, then the hidden activations");
     __shared__ __align__(16) uint16_t sx[kGateWaves][kGateTile][RS];
     const long long N = box_size(I);
     const long long ntiles = (N + kGateTile - 1) / kGateTile;
@@ -133,24 +137,24 @@ __global__ __launch_bounds__(64 * kGateWaves) void k_gate_infer(const double* __
     uint16_t(*row)[RS] = sx[wv];
 
     // weights as B fragments, biases and the last layer's weights of this lane's columns
-    bf16x4 w1[KC][4], w2[4][4];
+    bf16x8 w1[KC][4], w2[2][4];
     float b1[4], b2[4], w3[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int col = 16 * nt + r;
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc)
+        for (int kc = 0; kc < KC; ++kc) w1[kc][nt] = *reinterpret_cast<const bf16x8*>(&gp->W1[col][32 * kc + 8 * g4]);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) w1[kc][nt][q] = (short)gp->W1[col][16 * kc + 4 * g4 + q];
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) w2[kc][nt][q] = (short)gp->W2[col][16 * kc + 4 * g4 + q];
+        for (int kc = 0; kc < 2; ++kc) w2[kc][nt] = *reinterpret_cast<const bf16x8*>(&gp->W2[col][32 * kc + 8 * g4]);
         b1[nt] = gp->b1[col];
         b2[nt] = gp->b2[col];
         w3[nt] = bf2f(gp->w3[col]);
     }
     const float b3 = gp->b3, thr = gp->logit_thr;
+    // zero padding past the features that nothing else writes
+    constexpr int PZ = G::NFL > kHidden ? G::NFL : kHidden;
+#pragma unroll
+    for (int q = PZ; q < G::NFP; ++q) row[lane][q] = (uint16_t)0;
 
     for (long long t = (long long)blockIdx.x * kGateWaves + wv; t < ntiles; t += (long long)gridDim.x * kGateWaves) {
         const long long z = t * kGateTile + lane;
@@ -174,6 +178,7 @@ __global__ __launch_bounds__(64 * kGateWaves) void k_gate_infer(const double* __
             }
         };
         load_cross(0, val[0]);
+        uint32_t* rw = reinterpret_cast<uint32_t*>(row[lane]);
 #pragma unroll
         for (int v = 0; v < G::NV; ++v) {
             if (v + 1 < G::NV) load_cross(v + 1, val[(v + 1) & 1]);
@@ -182,12 +187,20 @@ __global__ __launch_bounds__(64 * kGateWaves) void k_gate_infer(const double* __
 #pragma unroll
             for (int q = 1; q < G::NC; ++q) { mx = fmax(mx, x[q]); mn = fmin(mn, x[q]); }
             const double rs = 1.0 / (mx - mn + 1e-12 * fmax(1.0, fabs(x[0])));
+            // FP64 -> FP32 -> BF16 (round to nearest even), two features per word
 #pragma unroll
-            for (int q = 0; q < G::NC; ++q)
-                row[lane][v * G::NC + q] = live ? f2bf((float)((x[q] - x[0]) * rs)) : (uint16_t)0;
+            for (int q = 0; q < G::NCB; q += 2) {
+                const float f0 = live ? (float)((x[q] - x[0]) * rs) : 0.0f;
+                const float f1 = (live && q + 1 < G::NC) ? (float)((x[q + 1] - x[0]) * rs) : 0.0f;
+                bf16x2 pr;
+                pr[0] = (__bf16)f0;
+                pr[1] = (__bf16)f1;
+                rw[(v * G::NCB + q) / 2] = __builtin_bit_cast(uint32_t, pr);
+            }
         }
+        // zero padding the hidden activations of the previous tile overwrote
 #pragma unroll
-        for (int q = G::NF; q < G::NFP; ++q) row[lane][q] = (uint16_t)0;
+        for (int q = G::NFL; q < kHidden; q += 2) rw[q / 2] = 0u;
         __builtin_amdgcn_s_waitcnt(0xc07f);       // lgkmcnt(0): this wavefront's rows are written
         __builtin_amdgcn_wave_barrier();
         for (int ms = 0; ms < kGateTile / 16; ++ms) {
@@ -198,12 +211,10 @@ __global__ __launch_bounds__(64 * kGateWaves) void k_gate_infer(const double* __
             for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
-                bf16x4 a;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) a[q] = (short)rs[r][16 * kc + 4 * g4 + q];
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&rs[r][32 * kc + 8 * g4]);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w1[kc][nt], acc[nt], 0, 0, 0);
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1[kc][nt], acc[nt], 0, 0, 0);
             }
             __builtin_amdgcn_s_waitcnt(0xc07f);
             __builtin_amdgcn_wave_barrier();
@@ -218,13 +229,11 @@ __global__ __launch_bounds__(64 * kGateWaves) void k_gate_infer(const double* __
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kc = 0; kc < 4; ++kc) {
-                bf16x4 a;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) a[q] = (short)rs[r][16 * kc + 4 * g4 + q];
+            for (int kc = 0; kc < 2; ++kc) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&rs[r][32 * kc + 8 * g4]);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w2[kc][nt], acc[nt], 0, 0, 0);
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w2[kc][nt], acc[nt], 0, 0, 0);
             }
             // layer 3: this lane's columns of rows 4 g4 + q, summed over the 16 lanes of the row group
             float part[4];
