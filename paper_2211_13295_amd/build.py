@@ -17,6 +17,9 @@ FLAGS = [
     # keep packed FP32 instructions out of the gfx950 code (the device pass
     # honours the feature; the host pass warns that it does not know it)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in ordinary VGPRs: the gate and training kernels feed them
+    # to VALU instructions, which would otherwise copy them out of AGPRs
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -966,11 +966,13 @@ static int set_gate_t(hog_grid* g, const float* prm, double theta)
     for (int o = 0; o < kHidden; ++o)
         for (int f = 0; f < G::NF; ++f)   // device feature layout: variable blocks of NCB columns
             h.W1[o][(f / G::NC) * G::NCB + f % G::NC] = host_bf16(prm[O::W1 + o * G::NF + f]);
+    // the inputs of layers 2 and 3 in the order the inference kernel's
+    // fragments hold them: position q carries hidden unit gate_unit(q)
     for (int o = 0; o < kHidden; ++o) {
         h.b1[o] = prm[O::B1 + o];
         h.b2[o] = prm[O::B2 + o];
-        h.w3[o] = host_bf16(prm[O::W3 + o]);
-        for (int q = 0; q < kHidden; ++q) h.W2[o][q] = host_bf16(prm[O::W2 + o * kHidden + q]);
+        h.w3[o] = host_bf16(prm[O::W3 + gate_unit(o)]);
+        for (int q = 0; q < kHidden; ++q) h.W2[o][q] = host_bf16(prm[O::W2 + o * kHidden + gate_unit(q)]);
     }
     h.b3 = prm[O::B3];
     h.logit_thr = (float)std::log(theta / (1.0 - theta));

@@ -100,27 +100,67 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-// Gate inference.  Each wavefront keeps the BF16 weights as MFMA operand
-// fragments in registers (loaded once) and loops over tiles of 64 interior
-// zones: lane l computes the features of zone l of the tile, one variable per
-// round, into an LDS row of the tile; then per 16-zone slice two BF16 MFMA
-// layers (16x16x32, FP32 accumulation) with the hidden activations written
-// back over the slice's feature rows, and the last layer as per-lane partial
-// dot products summed over the 16 lanes that share a row.  Operand layout of
+// Gate inference.  Each wavefront keeps the network as MFMA operand fragments
+// in registers (loaded once) and loops over tiles of 64 interior zones: lane l
+// computes the features of zone l of the tile, one variable per round, into an
+// LDS row of the tile (the first variable of the next tile is loaded before
+// the network runs on this one).  Per 16-zone slice the three layers run
+// transposed, as BF16 MFMAs with FP32 accumulation: H1^T = W1 X^T (A = W1,
+// B = the slice's feature rows), H2^T = W2 relu(H1)^T, logit = w3 relu(H2)^T
+// (A = w3 in row 0).  A layer's output fragment holds, for zone l%16, the
+// hidden units 16 nt + 4 (l/16) + q (q = 0..3) of output tile nt; these are
+// exactly the eight inputs per K chunk the next layer's B fragment needs for
+// the same zone once the next layer's weight columns are stored in the order
+// position 32 kc + 8 g + i <- unit 16 (2 kc + i/4) + 4 g + i%4 (gate_unit),
+// so the hidden activations never leave the registers.  The biases of the two
+// hidden layers (kept in LDS) are the accumulators' initial values.  Operand layout of
 // gfx950's 16x16x32 BF16 MFMA: A lane l holds A[l%16][8(l/16)+0..7], B lane l
 // holds B[8(l/16)+0..7][l%16], the result lane l holds D[4(l/16)+0..3][l%16].
 constexpr int kGateWaves = 4;   // wavefronts per workgroup
 constexpr int kGateTile = 64;   // zones per wavefront and tile
 
-template <int D>
-struct GateLds {
-    static constexpr int W = GateShape<D>::NFP > kHidden ? GateShape<D>::NFP : kHidden;
-    static constexpr int RS = W + 8;   // row stride (shorts): 16-byte aligned rows, padded
-};
+// Hidden unit whose activation sits at input position p of layers 2 and 3.
+__host__ __device__ constexpr int gate_unit(int p)
+{
+    return 16 * (2 * (p / 32) + (p % 8) / 4) + 4 * ((p % 32) / 8) + p % 4;
+}
 
 template <int D>
-__global__ __launch_bounds__(64 * kGateWaves) void k_gate_infer(const double* __restrict__ U, Pad p, Box I,
+struct GateLds {
+    static constexpr int RS = GateShape<D>::NFP + 8;   // row stride (shorts): 16-byte aligned rows, padded
+};
+
+// relu of an output fragment pair, rounded to BF16, as one B fragment: the
+// values are rounded in pairs, then the negative ones (sign bit set, so
+// negative as 16-bit integers) are replaced by zero with a packed integer max
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b)
+{
+    const bf16x2 pr = __builtin_convertvector(f32x2{a, b}, bf16x2);
+    const i16x2 m = __builtin_elementwise_max(__builtin_bit_cast(i16x2, pr), i16x2{0, 0});
+    return __builtin_bit_cast(uint32_t, m);
+}
+__device__ __forceinline__ bf16x8 gate_hidden(const f32x4& lo, const f32x4& hi)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 w = {relu_bf16x2(lo[0], lo[1]), relu_bf16x2(lo[2], lo[3]), relu_bf16x2(hi[0], hi[1]),
+                     relu_bf16x2(hi[2], hi[3])};
+    return __builtin_bit_cast(bf16x8, w);
+}
+
+// FP64 -> FP32 (round to nearest even), kept as an FP32 value so that the
+// following FP32 -> BF16 conversion rounds it again, as the definition does
+__device__ __forceinline__ float to_f32(double x)
+{
+    float f = (float)x;
+    asm volatile("" : "+v"(f));
+    return f;
+}
+
+template <int D>
+__global__ __launch_bounds__(64 * kGateWaves, 3) void k_gate_infer(const double* __restrict__ U, Pad p, Box I,
                                                                 const GateParams<D>* __restrict__ gp,
                                                                 unsigned char* __restrict__ flags,
                                                                 float* __restrict__ logits)
@@ -128,17 +168,21 @@ __global__ __launch_bounds__(64 * kGateWaves) void k_gate_infer(const double* __
     using G = GateShape<D>;
     constexpr int KC = G::NFP / 32;
     constexpr int RS = GateLds<D>::RS;
-    static_assert(RS >= kHidden && RS % 8 == 0, "rows hold the features, then the hidden activations");
     __shared__ __align__(16) uint16_t sx[kGateWaves][kGateTile][RS];
+    __shared__ __align__(16) float sb[2][kHidden];   // biases of the hidden layers
+    __shared__ __align__(16) uint16_t sw3[kHidden + 8];   // last layer's weights, then 8 zeros
     const long long N = box_size(I);
     const long long ntiles = (N + kGateTile - 1) / kGateTile;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int r = lane & 15, g4 = lane >> 4;
     uint16_t(*row)[RS] = sx[wv];
+    if (threadIdx.x < 2 * kHidden) sb[threadIdx.x / kHidden][threadIdx.x % kHidden] = threadIdx.x < kHidden
+        ? gp->b1[threadIdx.x] : gp->b2[threadIdx.x - kHidden];
+    if (threadIdx.x < kHidden + 8) sw3[threadIdx.x] = threadIdx.x < kHidden ? gp->w3[threadIdx.x] : 0;
+    __syncthreads();
 
-    // weights as B fragments, biases and the last layer's weights of this lane's columns
+    // A fragments of the first two weight matrices
     bf16x8 w1[KC][4], w2[2][4];
-    float b1[4], b2[4], w3[4];
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
         const int col = 16 * nt + r;
@@ -146,132 +190,121 @@ __global__ __launch_bounds__(64 * kGateWaves) void k_gate_infer(const double* __
         for (int kc = 0; kc < KC; ++kc) w1[kc][nt] = *reinterpret_cast<const bf16x8*>(&gp->W1[col][32 * kc + 8 * g4]);
 #pragma unroll
         for (int kc = 0; kc < 2; ++kc) w2[kc][nt] = *reinterpret_cast<const bf16x8*>(&gp->W2[col][32 * kc + 8 * g4]);
-        b1[nt] = gp->b1[col];
-        b2[nt] = gp->b2[col];
-        w3[nt] = bf2f(gp->w3[col]);
     }
     const float b3 = gp->b3, thr = gp->logit_thr;
-    // zero padding past the features that nothing else writes
-    constexpr int PZ = G::NFL > kHidden ? G::NFL : kHidden;
+    // the pad columns past the features stay zero
 #pragma unroll
-    for (int q = PZ; q < G::NFP; ++q) row[lane][q] = (uint16_t)0;
+    for (int q = G::NFL; q < G::NFP; q += 2) reinterpret_cast<uint32_t*>(row[lane])[q / 2] = 0u;
 
-    for (long long t = (long long)blockIdx.x * kGateWaves + wv; t < ntiles; t += (long long)gridDim.x * kGateWaves) {
+    const long long st[3] = {1, p.np[0], (long long)p.np[0] * p.np[1]};
+    auto centre = [&](long long t) {
         const long long z = t * kGateTile + lane;
         int i = 0, j = 0, k = 0;
-        const bool live = z < N;
-        if (live) box_ijk(I, z, i, j, k);
-        // features of zone `lane`, variable by variable; the cross of the next
-        // variable is loaded while the current one is scaled (two buffers)
-        const long long c0 = live ? pad_index(p, i, j, k) : pad_index(p, 0, 0, 0);
-        const long long st[3] = {1, p.np[0], (long long)p.np[0] * p.np[1]};
-        double val[2][G::NC];
-        auto load_cross = [&](int v, double* out) {
-            const double* u = U + v * p.vs + c0;
-            out[0] = u[0];
+        if (z < N) box_ijk(I, z, i, j, k);
+        else box_ijk(I, 0, i, j, k);   // a valid zone; its result is not stored
+        return pad_index(p, i, j, k);
+    };
+    auto load_cross = [&](long long c0, int v, double* out) {
+        const double* u = U + v * p.vs + c0;
+        out[0] = u[0];
 #pragma unroll
-            for (int ax = 0; ax < D; ++ax) {
-                out[1 + 4 * ax + 0] = u[-2 * st[ax]];
-                out[1 + 4 * ax + 1] = u[-1 * st[ax]];
-                out[1 + 4 * ax + 2] = u[1 * st[ax]];
-                out[1 + 4 * ax + 3] = u[2 * st[ax]];
-            }
-        };
-        load_cross(0, val[0]);
+        for (int ax = 0; ax < D; ++ax) {
+            out[1 + 4 * ax + 0] = u[-2 * st[ax]];
+            out[1 + 4 * ax + 1] = u[-1 * st[ax]];
+            out[1 + 4 * ax + 2] = u[1 * st[ax]];
+            out[1 + 4 * ax + 3] = u[2 * st[ax]];
+        }
+    };
+    double val[2][G::NC];
+    long long t = (long long)blockIdx.x * kGateWaves + wv;
+    const long long tstride = (long long)gridDim.x * kGateWaves;
+    long long c0 = centre(t);
+    if (t < ntiles) load_cross(c0, 0, val[0]);
+    for (; t < ntiles; t += tstride) {
+        // features of zone `lane`, variable by variable; the cross of the next
+        // variable is loaded while the current one is scaled (two buffers).
+        // Scale from the differences to the centre (max - min of the cross is
+        // the largest minus the smallest difference, the centre's being 0).
         uint32_t* rw = reinterpret_cast<uint32_t*>(row[lane]);
 #pragma unroll
         for (int v = 0; v < G::NV; ++v) {
-            if (v + 1 < G::NV) load_cross(v + 1, val[(v + 1) & 1]);
+            if (v + 1 < G::NV) load_cross(c0, v + 1, val[(v + 1) & 1]);
             const double* x = val[v & 1];
-            double mx = x[0], mn = x[0];
+            double d[G::NC];
+            d[0] = 0.0;
+            double mx = 0.0, mn = 0.0;
 #pragma unroll
-            for (int q = 1; q < G::NC; ++q) { mx = fmax(mx, x[q]); mn = fmin(mn, x[q]); }
-            const double rs = 1.0 / (mx - mn + 1e-12 * fmax(1.0, fabs(x[0])));
+            for (int q = 1; q < G::NC; ++q) {
+                d[q] = x[q] - x[0];
+                mx = fmax(mx, d[q]);
+                mn = fmin(mn, d[q]);
+            }
+            const double rs = recip(mx - mn + 1e-12 * fmax(1.0, fabs(x[0])));
             // FP64 -> FP32 -> BF16 (round to nearest even), two features per word
 #pragma unroll
             for (int q = 0; q < G::NCB; q += 2) {
-                const float f0 = live ? (float)((x[q] - x[0]) * rs) : 0.0f;
-                const float f1 = (live && q + 1 < G::NC) ? (float)((x[q + 1] - x[0]) * rs) : 0.0f;
-                bf16x2 pr;
-                pr[0] = (__bf16)f0;
-                pr[1] = (__bf16)f1;
+                const bf16x2 pr = __builtin_convertvector(
+                    f32x2{to_f32(d[q] * rs), (q + 1 < G::NC) ? to_f32(d[q + 1] * rs) : 0.0f}, bf16x2);
                 rw[(v * G::NCB + q) / 2] = __builtin_bit_cast(uint32_t, pr);
             }
         }
-        // zero padding the hidden activations of the previous tile overwrote
-#pragma unroll
-        for (int q = G::NFL; q < kHidden; q += 2) rw[q / 2] = 0u;
+        // the next tile's first variable is in flight while the network runs
+        const long long tn = t + tstride;
+        const long long c0n = centre(tn);
+        if (tn < ntiles) load_cross(c0n, 0, val[0]);
         __builtin_amdgcn_s_waitcnt(0xc07f);       // lgkmcnt(0): this wavefront's rows are written
         __builtin_amdgcn_wave_barrier();
-        for (int ms = 0; ms < kGateTile / 16; ++ms) {
-            uint16_t(*rs)[RS] = row + 16 * ms;
-            // layer 1: [16 x NFP] x [NFP x 64]
-            f32x4 acc[4];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int ms = 0; ms < kGateTile / 16; ++ms) {
+            const uint16_t* xr = row[16 * ms + r];
+            f32x4 a1[4], a2[4];
+            // biases of the output units this lane holds: units 16 nt + 4 g + 0..3
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) a1[nt] = *reinterpret_cast<const f32x4*>(&sb[0][16 * nt + 4 * g4]);
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&rs[r][32 * kc + 8 * g4]);
+                const bf16x8 x = *reinterpret_cast<const bf16x8*>(&xr[32 * kc + 8 * g4]);
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w1[kc][nt], acc[nt], 0, 0, 0);
+                    a1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1[kc][nt], x, a1[nt], 0, 0, 0);
             }
-            __builtin_amdgcn_s_waitcnt(0xc07f);
-            __builtin_amdgcn_wave_barrier();
-            // hidden layer 1 over the slice's feature rows (all reads of them are done)
+            const bf16x8 h1[2] = {gate_hidden(a1[0], a1[1]), gate_hidden(a1[2], a1[3])};
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
+            for (int nt = 0; nt < 4; ++nt) a2[nt] = *reinterpret_cast<const f32x4*>(&sb[1][16 * nt + 4 * g4]);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) rs[4 * g4 + q][16 * nt + r] = f2bf(fmaxf(acc[nt][q] + b1[nt], 0.0f));
-            __builtin_amdgcn_s_waitcnt(0xc07f);
-            __builtin_amdgcn_wave_barrier();
-            // layer 2: [16 x 64] x [64 x 64]
+            for (int kc = 0; kc < 2; ++kc)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int nt = 0; nt < 4; ++nt)
+                    a2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2[kc][nt], h1[kc], a2[nt], 0, 0, 0);
+            const bf16x8 h2[2] = {gate_hidden(a2[0], a2[1]), gate_hidden(a2[2], a2[3])};
+            // last layer: A = w3 in row 0, zero elsewhere
+            f32x4 a3 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kc = 0; kc < 2; ++kc) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&rs[r][32 * kc + 8 * g4]);
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, w2[kc][nt], acc[nt], 0, 0, 0);
+                const bf16x8 w3 = *reinterpret_cast<const bf16x8*>(&sw3[r == 0 ? 32 * kc + 8 * g4 : kHidden]);
+                a3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w3, h2[kc], a3, 0, 0, 0);
             }
-            // layer 3: this lane's columns of rows 4 g4 + q, summed over the 16 lanes of the row group
-            float part[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                float sum = 0.0f;
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) sum += bfround(fmaxf(acc[nt][q] + b2[nt], 0.0f)) * w3[nt];
-                part[q] = sum;
-            }
-#pragma unroll
-            for (int m = 1; m < 16; m <<= 1)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) part[q] += __shfl_xor(part[q], m, 16);
-            if (r < 4) {
-                const long long zz = t * kGateTile + 16 * ms + 4 * g4 + r;
-                float s = b3;
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (q == r) s += part[q];
-                if (zz < N) {
-                    if (flags) flags[zz] = s >= thr ? 1 : 0;
-                    if (logits) logits[zz] = s;
-                }
+            const long long zz = t * kGateTile + 16 * ms + r;
+            if (g4 == 0 && zz < N) {
+                const float s = a3[0] + b3;
+                if (flags) flags[zz] = s >= thr ? 1 : 0;
+                if (logits) logits[zz] = s;
             }
         }
+        c0 = c0n;
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
     }
 }
 
 // Workgroups of the inference kernel: enough tiles per wavefront to amortise
-// the weight loads, at most a few resident rounds of the device.
+// the weight loads, at most the three workgroups per CU that are resident at
+// once (166 VGPRs and 53 KB of LDS each).
 inline unsigned gate_blocks(long long nzones, int cus)
 {
     const long long tiles = (nzones + kGateTile - 1) / kGateTile;
     const long long want = (tiles + kGateWaves - 1) / kGateWaves;
-    const long long cap = (long long)cus * 4;
+    const long long cap = (long long)cus * 3;
     return (unsigned)(want < cap ? (want > 0 ? want : 1) : cap);
 }
 

@@ -421,6 +421,7 @@ struct PredShape {
     static constexpr int MS = Modes<D, P>::NS;
     static constexpr int MST = Modes<D, P>::NST;
     static constexpr int MT = MST - MS;              // modes with e >= 1
+    static constexpr int ME1 = binom(P - 1 + D, D);  // modes with e == 1
     static constexpr int NE = P;                     // flux time modes feeding a derivative
     static constexpr int NFULL = (NE - 1) * D * NV;  // projected rows per zone (e <= P - 2)
     static constexpr int NROWZ = NFULL + NV;         // + one folded row per variable (e = P - 1)
@@ -803,6 +804,27 @@ __device__ __forceinline__ void project_row_quad(const T* row, T* dst, int emax,
             }
 }
 
+// For the modes m in [LO, HI) and the variables v: use(m, v, q[m NV + v]),
+// with the wavefront-uniform LDS values read in batches of B, all reads of a
+// batch issued before any of its uses (one LDS round trip per batch instead
+// of a wait before nearly every use).
+template <int NV, int LO, int HI, int B, typename T, typename F>
+__device__ __forceinline__ void batched_modes(const T* q, F&& use)
+{
+    constexpr int N = (HI - LO) * NV;
+#pragma unroll
+    for (int b0 = 0; b0 < N; b0 += B) {
+        T qv[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            if (b0 + i < N) qv[i] = q[LO * NV + b0 + i];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+            if (b0 + i < N) use(LO + (b0 + i) / NV, (b0 + i) % NV, qv[i]);
+    }
+}
+
 template <int D, int P, typename T>
 struct LaneSetup {
     T px[P + 1], py[P + 1], pz[P + 1];
@@ -988,13 +1010,9 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 #pragma unroll
     for (int v = 0; v < NV; ++v) Q0[v] = T(0);
     if (active) {
-        const T* qz = sq + zs * MST * NV;
-#pragma unroll
-        for (int m = 0; m < MS; ++m) {
-            const T phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Q0[v] += qz[m * NV + v] * phi;
-        }
+        batched_modes<NV, 0, MS, 50>(sq + zs * MST * NV, [&](int m, int v, T q) {
+            Q0[v] += q * (px[M.a[m]] * py[M.b[m]] * pz[M.c[m]]);
+        });
     }
 
     for (int it = 0; it < P; ++it) {
@@ -1021,23 +1039,13 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
                 for (int e = 0; e < P; ++e)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) Qe[e][v] = T(0);
+                // the modes are ordered by time degree: those of degree 1 first
                 const T* qz = sq + zs * MST * NV;
-#pragma unroll
-                for (int m = MS; m < MST; ++m) {
-                    if (M.e[m] != 1) continue;
-                    const T phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) Qe[0][v] += qz[m * NV + v] * phi;
-                }
-                if (!deg1) {
-#pragma unroll
-                    for (int m = MS; m < MST; ++m) {
-                        if (M.e[m] == 1) continue;
-                        const T phi = px[M.a[m]] * py[M.b[m]] * pz[M.c[m]];
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) Qe[M.e[m] - 1][v] += qz[m * NV + v] * phi;
-                    }
-                }
+                auto acc_mode = [&](int m, int v, T q) {
+                    Qe[M.e[m] - 1][v] += q * (px[M.a[m]] * py[M.b[m]] * pz[M.c[m]]);
+                };
+                if (deg1) batched_modes<NV, MS, MS + S::ME1, 26>(qz, acc_mode);
+                else batched_modes<NV, MS, MST, 26>(qz, acc_mode);
                 T Racc[NE - 1][D][NV];
                 T Rtop[NV];
 #pragma unroll
@@ -1138,10 +1146,23 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
         // ---- assembly: for target (a, b, c, te), variable v,
         //   q = -sum_e I[e][te] sum_d lam_d g_{e,d,v}(rotated (a, b, c))
         //       - I[P-1][te] [a = b = c = 0] (folded row sum of v)
+        // (per target all LDS reads first, then the arithmetic; a lane
+        // without a target reads row 0 and stores nothing)
 #pragma unroll
         for (int r = 0; r < S::TPL; ++r) {
             const Target<D>& tq = tg[r];
-            if (!tq.valid) continue;
+            T gv[NE - 1][D], tv[NCH];
+            int ob[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) ob[d] = tq.valid ? tq.off[d] : 0;
+            const int otop = tq.valid ? tq.top : 0;
+#pragma unroll
+            for (int e = 0; e < NE - 1; ++e)
+#pragma unroll
+                for (int d = 0; d < D; ++d) gv[e][d] = sr[ob[d] + e * D * NV * RS];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) tv[ch] = sr[otop + ch * CH];
+            __builtin_amdgcn_sched_barrier(0);
             T acc = T(0);
 #pragma unroll
             for (int e = 0; e < NE - 1; ++e) {
@@ -1150,9 +1171,9 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 #pragma unroll
                 for (int et = 1; et <= P; ++et)
                     if (tq.te == et) ci = T(RL.I[e][et]);
-                T sum = lam[0] * sr[tq.off[0] + e * D * NV * RS];
+                T sum = lam[0] * gv[e][0];
 #pragma unroll
-                for (int d = 1; d < D; ++d) sum += lam[d] * sr[tq.off[d] + e * D * NV * RS];
+                for (int d = 1; d < D; ++d) sum += lam[d] * gv[e][d];
                 acc += ci * sum;
             }
             if (!first) {
@@ -1160,12 +1181,12 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 #pragma unroll
                 for (int et = 1; et <= P; ++et)
                     if (tq.te == et && tq.zero) ct = T(RL.I[NE - 1][et]);
-                T s = sr[tq.top];
+                T s = tv[0];
 #pragma unroll
-                for (int ch = 1; ch < NCH; ++ch) s += sr[tq.top + ch * CH];
+                for (int ch = 1; ch < NCH; ++ch) s += tv[ch];
                 acc += ct * s;
             }
-            sq[tq.soff] = -acc;
+            if (tq.valid) sq[tq.soff] = -acc;
         }
         __syncthreads();
     }
@@ -1213,13 +1234,9 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
         for (int e = 1; e <= P; ++e) bt[e] = bt[e - 1] * tau;
 #pragma unroll
         for (int v = 0; v < NV; ++v) Ufp[r][v] = T(0);
-        const T* qz = sq + z * MST * NV;
-#pragma unroll
-        for (int m = 0; m < MST; ++m) {
-            const T phi = bx[M.a[m]] * by[M.b[m]] * bz[M.c[m]] * bt[M.e[m]];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Ufp[r][v] += qz[m * NV + v] * phi;
-        }
+        batched_modes<NV, 0, MST, 50>(sq + z * MST * NV, [&](int m, int v, T q) {
+            Ufp[r][v] += q * (bx[M.a[m]] * by[M.b[m]] * bz[M.c[m]] * bt[M.e[m]]);
+        });
         if (positivity && !admissible<D, T>(Ufp[r], gm1)) atomicOr(&sbad[z], 1);
     }
     __syncthreads();
