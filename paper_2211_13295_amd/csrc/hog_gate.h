@@ -23,9 +23,10 @@ struct GateShape {
     static constexpr int NC = 4 * D + 1;          // cross: centre + 4 per axis
     static constexpr int NF = NV * NC;            // 36 (2D) / 65 (3D)
     // device layout of the features in inference: each variable's block padded
-    // to an even width (pairs of BF16 features are written as one word)
-    static constexpr int NCB = NC + 1;
-    static constexpr int NFL = NV * NCB;          // 40 (2D) / 70 (3D)
+    // to 16 columns (32 bytes, written as two 16-byte stores)
+    static constexpr int NCB = 16;
+    static_assert(NC <= NCB, "a cross fits one 16-column block");
+    static constexpr int NFL = NV * NCB;          // 64 (2D) / 80 (3D)
     static constexpr int NFP = (NFL + 31) / 32 * 32;   // padded to the MFMA K step (32)
     static constexpr int NPARAM = kHidden * NF + kHidden + kHidden * kHidden + kHidden + kHidden + 1;
 };
@@ -225,7 +226,9 @@ __global__ __launch_bounds__(64 * kGateWaves, 3) void k_gate_infer(const double*
         // variable is loaded while the current one is scaled (two buffers).
         // Scale from the differences to the centre (max - min of the cross is
         // the largest minus the smallest difference, the centre's being 0).
-        uint32_t* rw = reinterpret_cast<uint32_t*>(row[lane]);
+        // Each variable's 13 features and 3 zero pads are one 32-byte block of
+        // the row, written as two 16-byte stores.
+        uint16_t* rw = row[lane];
 #pragma unroll
         for (int v = 0; v < G::NV; ++v) {
             if (v + 1 < G::NV) load_cross(c0, v + 1, val[(v + 1) & 1]);
@@ -241,12 +244,18 @@ __global__ __launch_bounds__(64 * kGateWaves, 3) void k_gate_infer(const double*
             }
             const double rs = recip(mx - mn + 1e-12 * fmax(1.0, fabs(x[0])));
             // FP64 -> FP32 -> BF16 (round to nearest even), two features per word
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            uint32_t wd[G::NCB / 2];
 #pragma unroll
             for (int q = 0; q < G::NCB; q += 2) {
-                const bf16x2 pr = __builtin_convertvector(
-                    f32x2{to_f32(d[q] * rs), (q + 1 < G::NC) ? to_f32(d[q + 1] * rs) : 0.0f}, bf16x2);
-                rw[(v * G::NCB + q) / 2] = __builtin_bit_cast(uint32_t, pr);
+                const float f0 = q < G::NC ? to_f32(d[q] * rs) : 0.0f;
+                const float f1 = q + 1 < G::NC ? to_f32(d[q + 1] * rs) : 0.0f;
+                wd[q / 2] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{f0, f1}, bf16x2));
             }
+#pragma unroll
+            for (int k = 0; k < G::NCB / 8; ++k)
+                *reinterpret_cast<u32x4*>(&rw[v * G::NCB + 8 * k]) =
+                    u32x4{wd[4 * k], wd[4 * k + 1], wd[4 * k + 2], wd[4 * k + 3]};
         }
         // the next tile's first variable is in flight while the network runs
         const long long tn = t + tstride;

@@ -833,11 +833,24 @@ struct LaneSetup {
     Target<D> tg[PredShape<D, P>::TPL];
 };
 
+// Node of a lane: (ii, jj, kk) along x, y, z.  In 3D the z index is
+// (ii + jj + g) mod (P+1) in lane group g of (P+1)^2 lanes, so that the lanes of
+// a group hold distinct (ii, jj) and distinct (ii, kk) pairs: their stores
+// into the rows of every derivative axis then fall into distinct LDS banks.
+template <int D, int P>
+__device__ __forceinline__ void node_coords(int node, int& ii, int& jj, int& kk)
+{
+    constexpr int N1 = P + 1;
+    ii = node % N1;
+    jj = (node / N1) % N1;
+    kk = (D == 3) ? (ii + jj + node / (N1 * N1)) % N1 : 0;
+}
+
 template <int D, int P, typename T>
 __device__ __forceinline__ void node_position(LaneSetup<D, P, T>& L, int node, int ii, int jj, int kk)
 {
     constexpr int N1 = P + 1;
-    L.pos[0] = node;
+    L.pos[0] = ii + N1 * (jj + N1 * kk);
     if constexpr (D == 3) {
         L.pos[1] = jj + N1 * (ii + N1 * kk);
         L.pos[2] = kk + N1 * (ii + N1 * jj);
@@ -853,7 +866,8 @@ __device__ __forceinline__ void lane_setup_tables(LaneSetup<D, P, T>& L, int lan
     constexpr int N1 = P + 1;
     constexpr Rules<P> RL{};
     const int node = lane % S::NS;
-    const int ii = node % N1, jj = (node / N1) % N1, kk = (D == 3) ? node / (N1 * N1) : 0;
+    int ii, jj, kk;
+    node_coords<D, P>(node, ii, jj, kk);
     const double* nr[3] = {kNodeRows<P>.r[ii], kNodeRows<P>.r[jj], kNodeRows<P>.r[kk]};
 #pragma unroll
     for (int a = 0; a <= P; ++a) {
@@ -893,7 +907,8 @@ __device__ __forceinline__ void lane_setup_computed(LaneSetup<D, P, T>& L, int l
     constexpr Modes<D, P> M{};
     constexpr GIdx<D, P> GI{};
     const int node = lane % S::NS;
-    const int ii = node % N1, jj = (node / N1) % N1, kk = (D == 3) ? node / (N1 * N1) : 0;
+    int ii, jj, kk;
+    node_coords<D, P>(node, ii, jj, kk);
     const double xn = gl_node(N1, ii), yn = gl_node(N1, jj), zn = gl_node(N1, kk);
 #pragma unroll
     for (int a = 0; a <= P; ++a) {
