@@ -528,6 +528,62 @@ def stream_vs_in_core(hog, torch, args):
     return out
 
 
+def rank_block(hog, torch, args):
+    """One rank's share of the 384^3 four-quadrant problem split 2 x 2 x 2 over
+    eight devices: the 192^3 centre block with every axis external, its three
+    ghost layers on all sides cut from the whole state (what the neighbouring
+    blocks would send: 27.4 MB per step). Timed: the FP64 step of the block
+    (ghosts as given; a real rank refreshes them between steps) and the device
+    copy that packs a block with its ghost layers (hog_set_state_ext from
+    device memory), against the same block stepped as a standalone outflow grid."""
+    import icgen
+    N, m, g3 = C5_N, C5_N // 2, 3
+    lo = (N - m) // 2
+    pb = icgen.four_quadrant(n=N, seed=5, block=(lo - g3, m + 2 * g3))
+    pin = icgen.four_quadrant(n=N, seed=5, block=(lo, m))
+    steps = max(3, min(args.steps, 10))
+    ext = torch.from_numpy(np.ascontiguousarray(pb.U)).cuda()
+    out = {"metric": "zone-updates/s, one rank's block with every axis external", "unit": UNIT, "n_gpus": 1,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"centre {m}^3 block of the {N}^3 four-quadrant Riemann problem (2 x 2 x 2 split), "
+                                  "order 4 WENO+ADER, HLLC, FP64, ghost layers from the whole state"}}
+    g = hog.Grid(3, (m, m, m), 4, pin.h, gamma=pin.gamma, bc=("external",) * 3)
+    g.set_state_ext(ext)
+    dt = g.compute_dt()
+    g.step(dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.set_state_ext(ext)
+    torch.cuda.synchronize()
+    t_pack = (time.perf_counter() - t0) / steps
+    g.set_state_ext(ext)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.step(dt, want_next=False)
+    torch.cuda.synchronize()
+    t_ext = (time.perf_counter() - t0) / steps
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    h = hog.Grid.from_problem(pin, 4)
+    h.step(dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h.step(dt, want_next=False)
+    torch.cuda.synchronize()
+    t_out = (time.perf_counter() - t0) / steps
+    h.close()
+    ghost_bytes = ((m + 2 * g3) ** 3 - m ** 3) * 5 * 8
+    out.update({"value": m ** 3 / t_ext, "ms_per_step": t_ext * 1e3, "steps": steps,
+                "standalone_outflow_ms_per_step": t_out * 1e3,
+                "pack_with_ghosts_ms": t_pack * 1e3, "ghost_bytes_per_step": ghost_bytes,
+                "zones": m ** 3})
+    return out
+
+
 def cpu_baseline(order, seconds):
     """The CPU oracle (plain FP64 C, OpenMP over zones) timed on this host on a
     bounded sample: whole steps of the same 3D workload at 32^3 (per-zone work
@@ -1103,6 +1159,8 @@ def main():
     ap.add_argument("--host-round-trip", action="store_true",
                     help="instead of the benchmark line: steps with the paper's per-step host round trip of the "
                          "zone means vs the resident loop; prints one JSON line")
+    ap.add_argument("--rank-block", action="store_true",
+                    help="one rank's 192^3 block of the 384^3 headline problem with every axis external")
     ap.add_argument("--stream", action="store_true",
                     help="instead of the benchmark line: a host-resident 256^3 mesh streamed through the GPU in "
                          "slabs vs in core; prints one JSON line")
@@ -1129,7 +1187,7 @@ def main():
         sys.exit(2)
 
     special = (args.gate_ablation or args.second_order or args.ader_vs_rk or args.host_round_trip or args.stream
-               or args.shock_workload or args.vortex128 or args.gate_train)
+               or args.shock_workload or args.vortex128 or args.gate_train or args.rank_block)
     # the CPU baseline runs before this process touches the GPU
     cpu = None if (special or args.no_cpu_baseline) else cpu_baseline_c5(args.cpu_seconds)
 
@@ -1163,6 +1221,9 @@ def main():
         return
     if args.stream:
         print(json.dumps(stream_vs_in_core(hog, torch, args)), flush=True)
+        return
+    if args.rank_block:
+        print(json.dumps(rank_block(hog, torch, args)), flush=True)
         return
     if args.shock_workload:
         steps = 100 if args.shock_workload == "multiblast256" else 200

@@ -59,10 +59,12 @@ enum {
     HOG_ESTATE = -5      /* call out of order (e.g. step before set_state) */
 };
 
-/* Per-axis boundary.  HOG_EXTERNAL (last active axis only: z in 3D, y in 2D,
- * ADER stepping only): the caller supplies the three ghost layers below and
- * above the interior along that axis with hog_set_state_ext, e.g. from the
- * neighbouring slabs of a larger mesh (see hog_stream_*). */
+/* Per-axis boundary.  HOG_EXTERNAL (any active axis, ADER stepping only):
+ * the caller supplies the three ghost layers below and above the interior
+ * along that axis with hog_set_state_ext -- from the neighbouring slabs of a
+ * larger mesh (see hog_stream_*, which makes the last axis external), or, for
+ * one block of a mesh split over devices, from the neighbouring blocks
+ * (every axis external: the one exchange per step of Sec. I.1). */
 enum { HOG_PERIODIC = 0, HOG_OUTFLOW = 1, HOG_EXTERNAL = 2 };
 /* Riemann solver.  HOG_HLLEM and HOG_HLLI: the HLL flux with the dissipation
  * of the entropy and shear waves of Roe's linearisation reduced by Einfeldt's
@@ -167,12 +169,14 @@ int hog_set_state(hog_grid* g, const double* U, int layout, int where);
  * For a host buffer the call synchronises the stream.  Errors: HOG_EINVAL, HOG_ESTATE, HOG_EDEVICE. */
 int hog_get_state(hog_grid* g, double* U, int layout, int where);
 
-/* Like hog_set_state (SoA only) for a grid whose last axis is HOG_EXTERNAL:
- * U holds the interior and the three ghost layers below and above along that
- * axis, [nv][nz+6][ny][nx] in 3D or [nv][ny+6][nx] in 2D (layer 0 is the
- * lowest ghost layer).  The ghost layers are used as given by the next step;
- * the other axes' ghosts are filled from their boundary types as usual.
- * Errors: HOG_EINVAL (NULL, or the last axis not external), HOG_EDEVICE. */
+/* Like hog_set_state (SoA only) for a grid with HOG_EXTERNAL axes: U holds
+ * the interior grown by the three ghost layers below and above along every
+ * external axis, [nv][mz][my][mx] with m = n + 6 on an external axis and m = n
+ * otherwise (index 0 is the lowest ghost layer; edges and corners between
+ * external axes included).  The supplied ghost zones are used as given by the
+ * next step; the remaining ghosts are filled from their axes' boundary types
+ * (from the supplied values where they meet an external axis).
+ * Errors: HOG_EINVAL (NULL, or no axis external), HOG_EDEVICE. */
 int hog_set_state_ext(hog_grid* g, const double* U, int where);
 
 /* CFL time step of the current state, dt = cfl / max_zones sum_d

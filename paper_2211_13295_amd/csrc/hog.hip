@@ -76,11 +76,12 @@ int check_cfg(const hog_config* c)
         if (c->bc[d] != HOG_PERIODIC && c->bc[d] != HOG_OUTFLOW && c->bc[d] != HOG_EXTERNAL)
             return fail(HOG_EINVAL, "bad boundary type on axis %d", d);
     for (int d = 0; d < 3; ++d)
-        if (c->bc[d] == HOG_EXTERNAL && d != c->ndim - 1)
-            return fail(HOG_EINVAL, "an external boundary is supported on the last axis only (axis %d)", d);
-    if (c->bc[c->ndim - 1] == HOG_EXTERNAL && c->stepper != HOG_ADER)
-        return fail(HOG_EINVAL, "an external boundary needs the one-exchange ADER step (Runge-Kutta stages would "
-                                "need new ghost layers each)");
+        if (c->bc[d] == HOG_EXTERNAL && d >= c->ndim)
+            return fail(HOG_EINVAL, "axis %d is not active in %dD and cannot be external", d, c->ndim);
+    for (int d = 0; d < c->ndim; ++d)
+        if (c->bc[d] == HOG_EXTERNAL && c->stepper != HOG_ADER)
+            return fail(HOG_EINVAL, "an external boundary needs the one-exchange ADER step (Runge-Kutta stages would "
+                                    "need new ghost layers each)");
     if (c->precision != HOG_FP64 && c->precision != HOG_MIXED)
         return fail(HOG_EINVAL, "precision %d not supported", c->precision);
     if (c->precision == HOG_MIXED && c->debug)
@@ -130,10 +131,13 @@ void plan(const hog_config* c, Plan* P)
     P->pad.vs = (long long)P->pad.np[0] * P->pad.np[1] * P->pad.np[2];
     const int nx = P->n[0], ny = P->n[1], nz = P->n[2];
     P->I = make_box(0, 0, 0, nx, ny, nz);
-    P->E = P->I;
-    if (c->bc[nd - 1] == HOG_EXTERNAL) {
-        if (nd == 3) P->E = make_box(0, 0, -kGhostZones, nx, ny, nz + 2 * kGhostZones);
-        else P->E = make_box(0, -kGhostZones, 0, nx, ny + 2 * kGhostZones, 1);
+    // the zones a caller supplies: the interior grown by the ghost layers
+    // along every external axis (edges and corners between external axes too)
+    {
+        int lo[3] = {0, 0, 0}, ext[3] = {nx, ny, nz};
+        for (int d = 0; d < nd; ++d)
+            if (c->bc[d] == HOG_EXTERNAL) { lo[d] = -kGhostZones; ext[d] += 2 * kGhostZones; }
+        P->E = make_box(lo[0], lo[1], lo[2], ext[0], ext[1], ext[2]);
     }
     if (nd == 3) {
         P->AX = make_box(-1, -3, -3, nx + 2, ny + 6, nz + 6);
@@ -723,7 +727,9 @@ int hog_set_state_ext(hog_grid* g, const double* U, int where)
     if (!g || !U) return fail(HOG_EINVAL, "NULL argument");
     if (where != HOG_HOST && where != HOG_DEVICE) return fail(HOG_EINVAL, "unknown location %d", where);
     const Plan& L = g->P;
-    if (g->cfg.bc[L.nd - 1] != HOG_EXTERNAL) return fail(HOG_EINVAL, "the last axis is not external");
+    bool any = false;
+    for (int d = 0; d < L.nd; ++d) any = any || g->cfg.bc[d] == HOG_EXTERNAL;
+    if (!any) return fail(HOG_EINVAL, "no axis is external");
     const long long NE = box_size(L.E);
     const double* src = U;
     if (where == HOG_HOST) {
@@ -1326,7 +1332,8 @@ int stream_plan(const hog_config* m, int pn, StreamPlan* S)
     if (rc) return rc;
     const int nd = m->ndim;
     const int nlast = (nd == 3) ? m->nz : m->ny;
-    if (m->bc[nd - 1] == HOG_EXTERNAL) return fail(HOG_EINVAL, "the mesh's own last-axis boundary must be periodic or outflow");
+    for (int d = 0; d < nd; ++d)
+        if (m->bc[d] == HOG_EXTERNAL) return fail(HOG_EINVAL, "the mesh's own boundaries must be periodic or outflow");
     if (m->stepper != HOG_ADER) return fail(HOG_EINVAL, "streaming needs the one-exchange ADER step");
     if (m->debug) return fail(HOG_EINVAL, "no debug taps when streaming");
     if (pn < 1 || pn > nlast) return fail(HOG_EINVAL, "slab planes must be in [1, %d]", nlast);

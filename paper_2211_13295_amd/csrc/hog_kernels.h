@@ -127,13 +127,14 @@ __global__ __launch_bounds__(256) void k_ghost(double* __restrict__ U, Pad p, in
     long long r = idx / p.np[0];
     int j = (int)(r % p.np[1]) - p.off[1];
     int k = (int)(r / p.np[1]) - p.off[2];
-    // an external last axis (bc 2) keeps the ghost layers the caller supplied:
-    // zones outside only along it are left alone, the others are filled along
-    // the first axes from the supplied layer
-    const bool ext = (D == 3 ? bc2 : bc1) == 2;
-    const bool in01 = i >= 0 && i < n0 && (D == 3 ? (j >= 0 && j < n1) : true);
-    const bool inlast = (D == 3) ? (k >= 0 && k < n2) : (j >= 0 && j < n1);
-    if (in01 && (inlast || ext)) return;
+    // an external axis (bc 2) keeps the ghost layers the caller supplied: a
+    // zone inside the interior or on the supplied layers of every axis is left
+    // alone; the others are filled along the remaining axes from the supplied
+    // values (the source keeps the external coordinates)
+    const bool k0 = (i >= 0 && i < n0) || bc0 == 2;
+    const bool k1 = (j >= 0 && j < n1) || bc1 == 2;
+    const bool k2 = (D == 3) ? ((k >= 0 && k < n2) || bc2 == 2) : true;
+    if (k0 && k1 && k2) return;
     auto src = [](int x, int n, int bc) {
         if (bc == 2) return x;
         if (bc == 0) { x %= n; return x < 0 ? x + n : x; }
@@ -632,13 +633,13 @@ __device__ __forceinline__ void project_row(T* row, int emax)
 // Value held by the other lane of an even/odd lane pair (DPP quad_perm 1,0,3,2).
 __device__ __forceinline__ double pair_swap(double x)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0xB1, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0xB1, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0xB1, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0xB1, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ float pair_swap(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, true));
 }
 
 // project_row in 3D by a lane pair: lane `half` of the pair takes the node
@@ -729,13 +730,13 @@ __device__ __forceinline__ void project_row_pair(T* row, int emax, int half)
 // Value held by lane l ^ 2 within a lane quad (DPP quad_perm 2,3,0,1).
 __device__ __forceinline__ double quad_swap2(double x)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x4E, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x4E, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), 0x4E, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), 0x4E, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ float quad_swap2(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, true));
 }
 
 // project_row in 3D at fourth order by a lane quad: lane q of the quad takes
@@ -1047,7 +1048,7 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
             } else {
                 // The iterate of iteration it has time degree it (the first one is
                 // constant in time): in iteration 1 the modes of time degree >= 2
-                // are exactly zero, and their terms are skipped (uniform branches).
+                // are exactly zero, and their reads are skipped (uniform branch).
                 const bool deg1 = it == 1;
                 T Qe[P][NV];                        // time modes e = 1..P at the node
 #pragma unroll
@@ -1076,12 +1077,11 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
                     T U[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        T s = Qe[0][v];
-                        if (!deg1) {
-                            s = Qe[P - 1][v];
+                        // (in iteration 1 the higher time modes are zero, and the
+                        // Horner sum reduces exactly to the degree-1 one)
+                        T s = Qe[P - 1][v];
 #pragma unroll
-                            for (int e = P - 2; e >= 0; --e) s = s * T(RL.t[l]) + Qe[e][v];
-                        }
+                        for (int e = P - 2; e >= 0; --e) s = s * T(RL.t[l]) + Qe[e][v];
                         U[v] = Q0[v] + s * T(RL.t[l]);
                     }
                     T F[D][NV];

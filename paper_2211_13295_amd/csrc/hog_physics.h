@@ -46,11 +46,17 @@ __device__ __forceinline__ bool fluxes(const T* U, T gm1, T (*F)[D + 2])
     for (int d = 0; d < D; ++d) { u[d] = U[1 + d] * ir; ke += U[1 + d] * u[d]; }
     const T p = gm1 * (U[D + 1] - T(0.5) * ke);
     const T Ep = U[D + 1] + p;
+    // momentum fluxes m_k m_d / rho + p delta_kd: the off-diagonal product is
+    // shared by the two axes that need it
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         F[d][0] = U[1 + d];
+        F[d][1 + d] = U[1 + d] * u[d] + p;
 #pragma unroll
-        for (int k = 0; k < D; ++k) F[d][1 + k] = U[1 + k] * u[d] + (k == d ? p : T(0));
+        for (int k = 0; k < d; ++k) {
+            F[d][1 + k] = U[1 + k] * u[d];
+            F[k][1 + d] = F[d][1 + k];
+        }
         F[d][D + 1] = Ep * u[d];
     }
     return rho > T(0) && p > T(0) && isfinite(rho) && isfinite(p);

@@ -239,10 +239,21 @@ class Grid:
         assert a.size == self.nv * self.nzones
         _check(load().hog_set_state(self._h, a.ctypes.data_as(C.c_void_p), layout, HOST))
 
+    def ext_shape(self):
+        """Shape of the array hog_set_state_ext takes: SoA, each external axis
+        grown by the three ghost layers on both sides."""
+        bc = (self.cfg.bc[0], self.cfg.bc[1], self.cfg.bc[2])
+        n = [self.cfg.nx, self.cfg.ny, self.cfg.nz][: self.ndim]
+        m = [n[d] + 6 if bc[d] == BC["external"] else n[d] for d in range(self.ndim)]
+        return (self.nv,) + tuple(reversed(m))
+
     def set_state_ext(self, U):
-        """Interior plus the three ghost layers below and above along an
-        external last axis: SoA [v][n_last + 6][...] (host array or CUDA tensor)."""
+        """Interior plus the three ghost layers below and above along every
+        external axis: SoA [v][mz][my][mx] (host array or CUDA tensor)."""
         torch = self._torch
+        want = self.ext_shape()
+        if tuple(U.shape) != want:
+            raise ValueError(f"set_state_ext needs shape {want}, got {tuple(U.shape)}")
         if isinstance(U, torch.Tensor) and U.is_cuda:
             t = U.contiguous().to(torch.float64)
             _check(load().hog_set_state_ext(self._h, C.c_void_p(t.data_ptr()), DEVICE))

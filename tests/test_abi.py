@@ -82,21 +82,26 @@ def test_stepper_external_and_stream_configs_without_a_device():
     bad = [hog.make_config(3, (8, 8, 8), 4, (0.1,) * 3, stepper=5),
            hog.make_config(3, (8, 8, 8), 4, (0.1,) * 3, stepper="rk3", precision="mixed"),
            hog.make_config(3, (8, 8, 8), 4, (0.1,) * 3, stepper="rk3", debug=True),
-           hog.make_config(3, (8, 8, 8), 4, (0.1,) * 3, bc=("external", "periodic", "periodic")),
-           hog.make_config(3, (8, 8, 8), 4, (0.1,) * 3, bc=("periodic", "periodic", "external"), stepper="rk3")]
+           hog.make_config(3, (8, 8, 8), 4, (0.1,) * 3, bc=("external", "periodic", "periodic"), stepper="rk3"),
+           hog.make_config(3, (8, 8, 8), 4, (0.1,) * 3, bc=("periodic", "periodic", "external"), stepper="rk3"),
+           hog.make_config(2, (8, 8, 1), 3, (0.1,) * 3, bc=("periodic", "periodic", "external"))]
     for c in bad:
         with pytest.raises(hog.HogError) as e:
             hog.workspace_size(c)
         assert e.value.code == hog.HOG_EINVAL
     ext = hog.make_config(3, (8, 8, 8), 4, (0.1,) * 3, bc=("periodic", "periodic", "external"))
     assert hog.workspace_size(ext) > 0
+    # any axis may be external (a block of a mesh split over devices: all three)
+    for bc in (("external", "periodic", "periodic"), ("external", "external", "outflow"), ("external",) * 3):
+        assert hog.workspace_size(hog.make_config(3, (8, 8, 8), 4, (0.1,) * 3, bc=bc)) > 0
+    assert hog.workspace_size(hog.make_config(2, (8, 8, 1), 3, (0.1,) * 3, bc=("external", "external", "periodic"))) > 0
     mesh = hog.make_config(3, (8, 8, 20), 4, (0.1,) * 3)
     nb = ctypes.c_size_t(0)
     assert L.hog_stream_workspace_size(ctypes.byref(mesh), 6, ctypes.byref(nb)) == hog.HOG_OK
     # two slab grids of 6 planes and one of 2 (20 = 3 x 6 + 2) fit in less than the in-core plan
     assert 0 < nb.value < 2 * hog.workspace_size(mesh)
     for slab, cfg in ((0, mesh), (21, mesh), (6, hog.make_config(3, (8, 8, 20), 4, (0.1,) * 3, stepper="rk3")),
-                      (6, ext)):
+                      (6, ext), (6, hog.make_config(3, (8, 8, 20), 4, (0.1,) * 3, bc=("external", "periodic", "periodic")))):
         assert L.hog_stream_workspace_size(ctypes.byref(cfg), slab, ctypes.byref(nb)) == hog.HOG_EINVAL
 
 
