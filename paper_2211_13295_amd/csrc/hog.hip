@@ -336,8 +336,8 @@ int enqueue_step_t(hog_grid* g, double dt_user)
     {
         StageMark m(g, 3);
         for (int d = 0; d < D; ++d)
-            k_riemann<D, T><<<nblocks(box_size(L.FB[d]), 256), 256, 0, s>>>(FPa, L.R, L.FB[d], d, g->cfg.riemann,
-                                                                          g->cfg.gamma, g->F[d]);
+            launch_riemann<D, T>(g->cfg.riemann, nblocks(box_size(L.FB[d]), 256), s, FPa, L.R, L.FB[d], d,
+                                 g->cfg.gamma, g->F[d]);
     }
     {
         StageMark m(g, 4);
@@ -467,8 +467,8 @@ int enqueue_rk(hog_grid* g, double dt_user)
             {
                 StageMark m(g, 3);
                 for (int d = 0; d < D; ++d)
-                    k_riemann<D, double, (1 << (D - 1))><<<nblocks(box_size(L.FB[d]), 256), 256, 0, s>>>(
-                        FPa, L.R, L.FB[d], d, g->cfg.riemann, g->cfg.gamma, g->F[d]);
+                    launch_riemann<D, double, (1 << (D - 1))>(g->cfg.riemann, nblocks(box_size(L.FB[d]), 256), s,
+                                                              FPa, L.R, L.FB[d], d, g->cfg.gamma, g->F[d]);
             }
         }
         RkStage sg;

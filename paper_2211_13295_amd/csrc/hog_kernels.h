@@ -1280,9 +1280,11 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 // ------------------------------------------------------------------------
 // NPT points per face: 2^D for the ADER step (tangential axes and time),
 // 2^(D-1) for a Runge-Kutta stage (tangential axes only).
-template <int D, typename T, int NPT = (1 << D)>
+// SV: the Riemann solver (HOG_HLLC ... HOG_HLLI), a compile-time constant so
+// that each instance keeps only its own solver's registers and instructions.
+template <int D, typename T, int NPT, int SV>
 __global__ __launch_bounds__(256) void k_riemann(const T* __restrict__ FP, Box R, Box FB, int dir,
-                                                 int solver, double gamma, double* __restrict__ F)
+                                                 double gamma, double* __restrict__ F)
 {
     constexpr int NV = D + 2;
     const long long nF = box_size(FB), nR = box_size(R);
@@ -1304,12 +1306,26 @@ __global__ __launch_bounds__(256) void k_riemann(const T* __restrict__ FP, Box R
             UL[v] = FP[((long long)((dir * 2 + 1) * NPT + pt) * NV + v) * nR + zl];
             UR[v] = FP[((long long)((dir * 2 + 0) * NPT + pt) * NV + v) * nR + zr];
         }
-        riemann<D, T>(UL, UR, dir, solver, T(gamma), Fp);
+        riemann<D, T>(UL, UR, dir, SV, T(gamma), Fp);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fb[v] += w * (double)Fp[v];     // face average in FP64
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v * nF + f] = Fb[v];
+}
+
+// Launch k_riemann with the solver as a template argument.
+template <int D, typename T, int NPT = (1 << D)>
+inline void launch_riemann(int solver, unsigned blocks, hipStream_t s, const T* FP, Box R, Box FB, int dir,
+                           double gamma, double* F)
+{
+    switch (solver) {
+    case 0: k_riemann<D, T, NPT, 0><<<blocks, 256, 0, s>>>(FP, R, FB, dir, gamma, F); break;
+    case 1: k_riemann<D, T, NPT, 1><<<blocks, 256, 0, s>>>(FP, R, FB, dir, gamma, F); break;
+    case 2: k_riemann<D, T, NPT, 2><<<blocks, 256, 0, s>>>(FP, R, FB, dir, gamma, F); break;
+    case 3: k_riemann<D, T, NPT, 3><<<blocks, 256, 0, s>>>(FP, R, FB, dir, gamma, F); break;
+    default: k_riemann<D, T, NPT, 4><<<blocks, 256, 0, s>>>(FP, R, FB, dir, gamma, F); break;
+    }
 }
 
 // ------------------------------------------------------------------------
