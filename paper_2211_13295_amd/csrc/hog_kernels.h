@@ -392,16 +392,20 @@ __global__ __launch_bounds__(256) void k_recon_z(const T* __restrict__ B, Box BY
 
 // ------------------------------------------------------------------------
 // a4: ADER predictor.  One wavefront per zone group.
-// Node phase: lane = (zone slot, spatial Gauss node); each lane keeps the
-// time-independent part of q at its node in registers, evaluates the time
-// modes from LDS, forms the physical fluxes at every time node and contracts
-// them against the shifted-Legendre time basis.
+// Node phase: lane = (zone slot, spatial Gauss node; in 3D the node's z index
+// is shifted per lane group so that the row stores below hit distinct LDS
+// banks); each lane keeps the time-independent part of q at its node in
+// registers, evaluates the time modes from LDS (wavefront-uniform values,
+// read in batches), forms the physical fluxes at every time node and
+// contracts them against the shifted-Legendre time basis.
 // Projection phase: the contracted fluxes of the flux time modes e <= P - 2
 // go to LDS as one row per (zone, e, axis d, variable), with the nodes of the
-// row stored so that axis d is the fastest one.  One lane owns a row and
-// projects it in registers with axis d contracted first, keeping only the
-// coefficients the update uses (degree >= 1 along d); it truncates them to
-// total space-time degree P and applies the derivative along d.  The top
+// row stored so that axis d is the fastest one.  A lane (2D), a lane pair
+// (3D) or, in the first iteration of the FP64 fourth-order instance, a lane
+// quad owns a row and projects it in registers with axis d contracted first,
+// keeping only the coefficients the update uses (degree >= 1 along d); it
+// truncates them to total space-time degree P and applies the derivative
+// along d.  The top
 // flux time mode e = P - 1 only reaches the zone-constant spatial modes (its
 // degree-1 coefficients along each axis), so the node phase folds its axes
 // into one weighted node value per variable and the projection phase sums
@@ -720,13 +724,6 @@ __device__ __forceinline__ void project_row_pair(T* row, int emax, int half)
             }
 }
 
-// Per-lane constants of the predictor: the monic Legendre basis at the lane's
-// node along each axis, the node's position in the rows of each derivative
-// axis, the node weight of the folded top flux time mode, and the new-mode
-// targets the lane owns.  Two ways to obtain the same values: read from the
-// compile-time tables (fewer VALU instructions: used by the FP64 instance,
-// which runs at two wavefronts per SIMD) or computed in registers (used by the
-// FP32 instance, measured faster at its four wavefronts per SIMD).
 // Value held by lane l ^ 2 within a lane quad (DPP quad_perm 2,3,0,1).
 __device__ __forceinline__ double quad_swap2(double x)
 {
@@ -826,6 +823,13 @@ __device__ __forceinline__ void batched_modes(const T* q, F&& use)
     }
 }
 
+// Per-lane constants of the predictor: the monic Legendre basis at the lane's
+// node along each axis, the node's position in the rows of each derivative
+// axis, the node weight of the folded top flux time mode, and the new-mode
+// targets the lane owns.  Two ways to obtain the same values: read from the
+// compile-time tables (fewer VALU instructions: used by the FP64 instance,
+// which runs at two wavefronts per SIMD) or computed in registers (used by the
+// FP32 instance, measured faster at its four wavefronts per SIMD).
 template <int D, int P, typename T>
 struct LaneSetup {
     T px[P + 1], py[P + 1], pz[P + 1];

@@ -2,6 +2,8 @@
 boundary it is built on: the streamed step must equal the in-core step of the
 whole mesh zone for zone (bitwise: every zone sees the same stencil and the
 same arithmetic), over several steps with the CFL dt, and match the oracle."""
+import os
+
 import numpy as np
 import pytest
 
@@ -10,6 +12,7 @@ import oracle
 from tests.test_gpu_parity import REL_L1, note, rel_l1
 
 pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module")
@@ -68,6 +71,7 @@ BLOCK_CASES = [
     (3, 3, "fp64", ("outflow", "periodic", "outflow"), (1,)),
     (3, 2, "fp64", ("periodic",) * 3, (0, 1, 2)),
     (2, 4, "fp64", ("periodic", "periodic", "outflow"), (0, 1)),
+    (3, 4, "mixed+gate", ("periodic",) * 3, (0, 1, 2)),
 ]
 
 
@@ -80,10 +84,22 @@ def test_external_block_matches_in_core(hog, ndim, order, precision, bc, axes):
     the whole mesh does: the same stencils, the same arithmetic."""
     n = (20, 17, 15) if ndim == 3 else (36, 30, 1)
     note(f"external block ndim={ndim} order={order} {precision} bc={bc} axes={axes}")
-    pb = icgen.random_smooth(n=n, ndim=ndim, seed=7 + order, amp=0.3, bc="periodic", h=(0.1, 0.08, 0.11))
+    # (a gentler state for the gated case, so that the network gates a good share of the zones)
+    amp = 0.02 if precision == "mixed+gate" else 0.3
+    pb = icgen.random_smooth(n=n, ndim=ndim, seed=7 + order, amp=amp, bc="periodic", h=(0.1, 0.08, 0.11))
     pb.bc = tuple(bc)
     riemann = "hll" if order == 2 else "hllc"
+    gate = None
+    if precision == "mixed+gate":
+        # the trained network: a block's gate flags see the same 13-zone crosses
+        # (through the supplied ghost layers) as the mesh's
+        z = np.load(os.path.join(ROOT, "paper_2211_13295_amd", "gate_o4_3d.npz"))
+        gate = (z["params"], float(z["theta"]))
+        precision = "mixed"
     g = hog.Grid.from_problem(pb, order, precision=precision, riemann=riemann)
+    if gate is not None:
+        g.set_gate(gate[0], theta=gate[1])
+        note(f"gated fraction {float(g.gate_eval()[1].mean()):.3f}")
     dt = g.compute_dt()
     g.step(dt)
     full = g.get_state()
@@ -114,6 +130,8 @@ def test_external_block_matches_in_core(hog, ndim, order, precision, bc, axes):
         nb.append(1)
     import torch
     b = hog.Grid(ndim, tuple(nb), order, pb.h, gamma=pb.gamma, bc=tuple(bcb), precision=precision, riemann=riemann)
+    if gate is not None:
+        b.set_gate(gate[0], theta=gate[1])
     with pytest.raises(ValueError):
         b.set_state_ext(pb.U)
     b.set_state_ext(torch.from_numpy(np.ascontiguousarray(ext)).cuda())
