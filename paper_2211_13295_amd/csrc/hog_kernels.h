@@ -868,17 +868,19 @@ template <int D, int P, typename T>
 __device__ __forceinline__ void lane_setup_tables(LaneSetup<D, P, T>& L, int lane, const T* lam)
 {
     using S = PredShape<D, P>;
-    constexpr int N1 = P + 1;
     constexpr Rules<P> RL{};
     const int node = lane % S::NS;
     int ii, jj, kk;
     node_coords<D, P>(node, ii, jj, kk);
     const double* nr[3] = {kNodeRows<P>.r[ii], kNodeRows<P>.r[jj], kNodeRows<P>.r[kk]};
+    // the degree-0 basis function is 1 at every node: a literal, so that the
+    // basis products of the modes constant along an axis cost no multiply
+    L.px[0] = L.py[0] = L.pz[0] = T(1);
 #pragma unroll
-    for (int a = 0; a <= P; ++a) {
+    for (int a = 1; a <= P; ++a) {
         L.px[a] = T(nr[0][a]);
         L.py[a] = T(nr[1][a]);
-        L.pz[a] = (D == 3) ? T(nr[2][a]) : T(a == 0 ? 1 : 0);
+        L.pz[a] = (D == 3) ? T(nr[2][a]) : T(0);
     }
     node_position<D, P, T>(L, node, ii, jj, kk);
 #pragma unroll
@@ -1286,6 +1288,8 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 // 2^(D-1) for a Runge-Kutta stage (tangential axes only).
 // SV: the Riemann solver (HOG_HLLC ... HOG_HLLI), a compile-time constant so
 // that each instance keeps only its own solver's registers and instructions.
+// The FP64 instances divide by Newton-refined reciprocals (a quarter fewer
+// instructions for HLLC; a few ulp instead of correctly rounded quotients).
 template <int D, typename T, int NPT, int SV>
 __global__ __launch_bounds__(256) void k_riemann(const T* __restrict__ FP, Box R, Box FB, int dir,
                                                  double gamma, double* __restrict__ F)
@@ -1310,7 +1314,7 @@ __global__ __launch_bounds__(256) void k_riemann(const T* __restrict__ FP, Box R
             UL[v] = FP[((long long)((dir * 2 + 1) * NPT + pt) * NV + v) * nR + zl];
             UR[v] = FP[((long long)((dir * 2 + 0) * NPT + pt) * NV + v) * nR + zr];
         }
-        riemann<D, T>(UL, UR, dir, SV, T(gamma), Fp);
+        riemann<D, T, sizeof(T) == 8>(UL, UR, dir, SV, T(gamma), Fp);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fb[v] += w * (double)Fp[v];     // face average in FP64
     }

@@ -23,8 +23,10 @@ struct WenoArgs {
 // FP64 reciprocal from the hardware estimate refined by two Newton steps
 // r <- r + r (1 - x r) (within a few ulp of 1/x; 0, negative or non-finite x
 // give a non-finite or negative result, which the admissibility check below
-// rejects).  FP32 keeps the correctly rounded division, which measured faster
-// in the FP32 predictor.
+// rejects).  Used for the FP64 fluxes of the predictor, the FP64 Riemann
+// solvers and the nonlinear WENO weights (whose denominators are at least
+// eps^2 > 0).  FP32 keeps the correctly rounded division, which measured
+// faster in the FP32 predictor.
 __device__ __forceinline__ double recip(double x)
 {
     double r = __builtin_amdgcn_rcp(x);
@@ -242,8 +244,9 @@ __device__ __forceinline__ void weno1d(const double* v, double* c, const WenoArg
             const double bL = wa.eps + (l1 * l1 + k13_3 * l2 * l2);
             const double bC = wa.eps + (m1 * m1 + k13_3 * m2 * m2);
             const double bR = wa.eps + (r1 * r1 + k13_3 * r2 * r2);
-            const double aL = wa.g[0] / (bL * bL), aC = wa.g[1] / (bC * bC), aR = wa.g[2] / (bR * bR);
-            const double is = 1.0 / (aL + aC + aR);
+            const double aL = wa.g[0] * recip(bL * bL), aC = wa.g[1] * recip(bC * bC),
+                         aR = wa.g[2] * recip(bR * bR);
+            const double is = recip(aL + aC + aR);
             wL = aL * is; wC = aC * is; wR = aR * is;
         }
         c[1] = wL * l1 + wC * m1 + wR * r1;
@@ -260,11 +263,12 @@ __device__ __forceinline__ void weno1d(const double* v, double* c, const WenoArg
             const double bL = wa.eps + (l1 * l1 + k13_3 * l2 * l2);
             const double bC = wa.eps + (m1 * m1 + k13_3 * m2 * m2);
             const double bR = wa.eps + (r1 * r1 + k13_3 * r2 * r2);
-            const double aH = gH / (bH * bH), aL = gL / (bL * bL), aC = gC / (bC * bC), aR = gR / (bR * bR);
-            const double is = 1.0 / (aH + aL + aC + aR);
+            const double aH = gH * recip(bH * bH), aL = gL * recip(bL * bL), aC = gC * recip(bC * bC),
+                         aR = gR * recip(bR * bR);
+            const double is = recip(aH + aL + aC + aR);
             wH = aH * is; wL = aL * is; wC = aC * is; wR = aR * is;
         }
-        const double r = wH / gH;
+        const double r = wH * recip(gH);
         c[1] = r * (h1 - gL * l1 - gC * m1 - gR * r1) + wL * l1 + wC * m1 + wR * r1;
         c[2] = r * (h2 - gL * l2 - gC * m2 - gR * r2) + wL * l2 + wC * m2 + wR * r2;
         c[3] = r * h3;
@@ -290,8 +294,9 @@ __device__ __forceinline__ void weno1d_mixed(const double* v, float* c, const We
         float wL = (float)wa.g[0], wC = (float)wa.g[1], wR = (float)wa.g[2];
         if (!wa.linear) {
             const double bL = wa.eps + is2(l1, l2), bC = wa.eps + is2(m1, m2), bR = wa.eps + is2(r1, r2);
-            const double aL = wa.g[0] / (bL * bL), aC = wa.g[1] / (bC * bC), aR = wa.g[2] / (bR * bR);
-            const double is = 1.0 / (aL + aC + aR);
+            const double aL = wa.g[0] * recip(bL * bL), aC = wa.g[1] * recip(bC * bC),
+                         aR = wa.g[2] * recip(bR * bR);
+            const double is = recip(aL + aC + aR);
             wL = (float)(aL * is); wC = (float)(aC * is); wR = (float)(aR * is);
         }
         c[1] = wL * l1 + wC * m1 + wR * r1;
@@ -307,10 +312,10 @@ __device__ __forceinline__ void weno1d_mixed(const double* v, float* c, const We
             const double s1 = (double)h1 + 0.1 * (double)h3;
             const double bH = wa.eps + (s1 * s1 + k13_3 * (double)h2 * h2 + (781.0 / 20.0) * (double)h3 * h3);
             const double bL = wa.eps + is2(l1, l2), bC = wa.eps + is2(m1, m2), bR = wa.eps + is2(r1, r2);
-            const double aH = gH / (bH * bH), aL = wa.g[1] / (bL * bL), aC = wa.g[2] / (bC * bC),
-                         aR = wa.g[3] / (bR * bR);
-            const double is = 1.0 / (aH + aL + aC + aR);
-            ratio = aH * is / gH;
+            const double aH = gH * recip(bH * bH), aL = wa.g[1] * recip(bL * bL), aC = wa.g[2] * recip(bC * bC),
+                         aR = wa.g[3] * recip(bR * bR);
+            const double is = recip(aH + aL + aC + aR);
+            ratio = aH * is * recip(gH);
             wL = (float)(aL * is); wC = (float)(aC * is); wR = (float)(aR * is);
             wH = (float)(aH * is);
         }
