@@ -1288,8 +1288,9 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
 // 2^(D-1) for a Runge-Kutta stage (tangential axes only).
 // SV: the Riemann solver (HOG_HLLC ... HOG_HLLI), a compile-time constant so
 // that each instance keeps only its own solver's registers and instructions.
-// The FP64 instances divide by Newton-refined reciprocals (a quarter fewer
-// instructions for HLLC; a few ulp instead of correctly rounded quotients).
+// Divisions by Newton-refined reciprocals (a few ulp instead of correctly
+// rounded quotients: a quarter fewer instructions for FP64 HLLC) and, in FP32,
+// the hardware square root.
 template <int D, typename T, int NPT, int SV>
 __global__ __launch_bounds__(256) void k_riemann(const T* __restrict__ FP, Box R, Box FB, int dir,
                                                  double gamma, double* __restrict__ F)
@@ -1314,7 +1315,7 @@ __global__ __launch_bounds__(256) void k_riemann(const T* __restrict__ FP, Box R
             UL[v] = FP[((long long)((dir * 2 + 1) * NPT + pt) * NV + v) * nR + zl];
             UR[v] = FP[((long long)((dir * 2 + 0) * NPT + pt) * NV + v) * nR + zr];
         }
-        riemann<D, T, sizeof(T) == 8>(UL, UR, dir, SV, T(gamma), Fp);
+        riemann<D, T, true>(UL, UR, dir, SV, T(gamma), Fp);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fb[v] += w * (double)Fp[v];     // face average in FP64
     }
