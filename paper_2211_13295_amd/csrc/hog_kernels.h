@@ -646,6 +646,32 @@ __device__ __forceinline__ float pair_swap(float x)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, true));
 }
 
+// out[a] = sum over the Gauss nodes h of proj[a][h] v[h] for a0 <= a <= a1.
+// The nodes are symmetric about 0 and the monic Legendre basis has the parity
+// of its degree, so proj[a][N1-1-h] = (-1)^a proj[a][h]: the sums and
+// differences of the node pairs are formed once and shared by all modes (a
+// four-node line: 4 additions + 2 multiply-adds per mode instead of 4).
+template <int P, typename T>
+__device__ __forceinline__ void project_line(const T (&v)[P + 1], T (&out)[P + 1], int a0, int a1)
+{
+    constexpr int N1 = P + 1, H = N1 / 2;
+    constexpr Rules<P> RL{};
+    T sp[H > 0 ? H : 1], sm[H > 0 ? H : 1];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        sp[h] = v[h] + v[N1 - 1 - h];
+        sm[h] = v[h] - v[N1 - 1 - h];
+    }
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        if (a < a0 || a > a1) continue;
+        T s = (N1 % 2 == 1 && a % 2 == 0) ? T(RL.proj[a][H]) * v[H] : T(0);
+#pragma unroll
+        for (int h = 0; h < H; ++h) s += T(RL.proj[a][h]) * (a % 2 ? sm[h] : sp[h]);
+        out[a] = s;
+    }
+}
+
 // project_row in 3D by a lane pair: lane `half` of the pair takes the node
 // planes half, half + 2, ... along the second other axis, the pair adds its
 // two partial sums (the same two numbers on both lanes, so both hold the same
@@ -675,30 +701,50 @@ __device__ __forceinline__ void project_row_pair(T* row, int emax, int half)
 #pragma unroll
             for (int h = 0; h < N1; ++h) x[o][h] = live ? row[(p2 * N1 + o) * N1 + h] : T(0);
         T t1[N1][N1];         // [o1 node][hi]
+        T s1[N1][N1];         // [hi][o1]
+        if constexpr (sizeof(T) == 8) {
 #pragma unroll
-        for (int o = 0; o < N1; ++o)
+            for (int o = 0; o < N1; ++o) project_line<P, T>(x[o], t1[o], 1, P);
 #pragma unroll
             for (int hi = 1; hi <= P; ++hi) {
-                T s = T(0);
+                T col[N1];
 #pragma unroll
-                for (int h = 0; h < N1; ++h)
-                    if (RL.proj[hi][h] != 0.0) s += T(RL.proj[hi][h]) * x[o][h];
-                t1[o][hi] = s;
+                for (int o = 0; o < N1; ++o) col[o] = t1[o][hi];
+                project_line<P, T>(col, s1[hi], 0, P - hi);
             }
+        } else {
+            // FP32: the plain node sums (the node-pair form measured no faster
+            // in this instance)
+#pragma unroll
+            for (int o = 0; o < N1; ++o)
+#pragma unroll
+                for (int hi = 1; hi <= P; ++hi) {
+                    T s = T(0);
+#pragma unroll
+                    for (int h = 0; h < N1; ++h)
+                        if (RL.proj[hi][h] != 0.0) s += T(RL.proj[hi][h]) * x[o][h];
+                    t1[o][hi] = s;
+                }
+#pragma unroll
+            for (int hi = 1; hi <= P; ++hi)
+#pragma unroll
+                for (int o1 = 0; hi + o1 <= P; ++o1) {
+                    T s = T(0);
+#pragma unroll
+                    for (int o = 0; o < N1; ++o)
+                        if (RL.proj[o1][o] != 0.0) s += T(RL.proj[o1][o]) * t1[o][hi];
+                    s1[hi][o1] = s;
+                }
+        }
 #pragma unroll
         for (int hi = 1; hi <= P; ++hi)
 #pragma unroll
-            for (int o1 = 0; hi + o1 <= P; ++o1) {
-                T s = T(0);
-#pragma unroll
-                for (int o = 0; o < N1; ++o)
-                    if (RL.proj[o1][o] != 0.0) s += T(RL.proj[o1][o]) * t1[o][hi];
+            for (int o1 = 0; hi + o1 <= P; ++o1)
 #pragma unroll
                 for (int o2 = 0; hi + o1 + o2 <= P; ++o2) {
-                    if (t == 0) c[hi][o1][o2] = w[o2] * s;
-                    else c[hi][o1][o2] += w[o2] * s;
+                    if (t == 0) c[hi][o1][o2] = w[o2] * s1[hi][o1];
+                    else c[hi][o1][o2] += w[o2] * s1[hi][o1];
                 }
-            }
     }
 #pragma unroll
     for (int hi = 1; hi <= P; ++hi)
@@ -764,30 +810,24 @@ __device__ __forceinline__ void project_row_quad(const T* row, T* dst, int emax,
         for (int h = 0; h < N1; ++h) x[o][h] = row[(q * N1 + o) * N1 + h];
     T t1[N1][N1];             // [o1 node][hi]
 #pragma unroll
-    for (int o = 0; o < N1; ++o)
-#pragma unroll
-        for (int hi = 1; hi <= P; ++hi) {
-            T s = T(0);
-#pragma unroll
-            for (int h = 0; h < N1; ++h) s += T(RL.proj[hi][h]) * x[o][h];
-            t1[o][hi] = s;
-        }
+    for (int o = 0; o < N1; ++o) project_line<P, T>(x[o], t1[o], 1, P);
     T c[N1][N1][N1];          // [hi][o1][o2], used for hi >= 1, hi + o1 + o2 <= P
 #pragma unroll
-    for (int hi = 1; hi <= P; ++hi)
+    for (int hi = 1; hi <= P; ++hi) {
+        T col[N1], s1[N1];
 #pragma unroll
-        for (int o1 = 0; hi + o1 <= P; ++o1) {
-            T s = T(0);
+        for (int o = 0; o < N1; ++o) col[o] = t1[o][hi];
+        project_line<P, T>(col, s1, 0, P - hi);
 #pragma unroll
-            for (int o = 0; o < N1; ++o) s += T(RL.proj[o1][o]) * t1[o][hi];
+        for (int o1 = 0; hi + o1 <= P; ++o1)
 #pragma unroll
             for (int o2 = 0; hi + o1 + o2 <= P; ++o2) {
-                T own = w[o2] * s;
+                T own = w[o2] * s1[o1];
                 own = own + pair_swap(own);
                 own = own + quad_swap2(own);
                 c[hi][o1][o2] = (hi + o1 + o2 > emax) ? T(0) : own;
             }
-        }
+    }
 #pragma unroll
     for (int o2 = 0; o2 <= P - 1; ++o2)
 #pragma unroll
