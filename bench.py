@@ -178,8 +178,8 @@ def traffic_record(second_order=False, kind=None):
 
 
 PMC_COMMAND = ("export TMPDIR=/tmp; timeout -s KILL 240 rocprofv3 --pmc {ctr} --kernel-include-regex "
-               "\"k_predict|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --steps 2 "
-               "--warmup 0 --no-cpu-baseline --no-mixed --copy-calibration")
+               "\"k_predict|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --vortex128 "
+               "--steps 2 --warmup 0 --no-cpu-baseline --no-mixed --copy-calibration")
 PMC_COMMAND_C5 = ("export TMPDIR=/tmp; timeout -s KILL 300 rocprofv3 --pmc {ctr} --kernel-include-regex "
                   "\"k_predict|elementwise\" -f csv -d gpurun_out/prof_{tag} -o {tag} -- python3 bench.py --steps 1 "
                   "--warmup 0 --no-cpu-baseline --no-mixed --no-vortex128 --copy-calibration")
