@@ -1001,8 +1001,10 @@ __device__ __forceinline__ void lane_setup_computed(LaneSetup<D, P, T>& L, int l
     }
 }
 
+// Occupancy: FP64 two wavefronts per SIMD (up to 256 VGPRs); FP32 four, the
+// most its LDS rows allow, so its registers are bounded to 128.
 template <int D, int P, typename T>
-__global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box R,
+__global__ __launch_bounds__(64, sizeof(T) == 8 ? 2 : 4) void k_predict(const T* __restrict__ W, Box R,
                                                    StepInfo* __restrict__ info, double gamma, int positivity,
                                                    T* __restrict__ FP, T* __restrict__ Qout)
 {
@@ -1077,6 +1079,9 @@ __global__ __launch_bounds__(64, 2) void k_predict(const T* __restrict__ W, Box 
         });
     }
 
+    // the P iterations unrolled: each one specialised (first, degree 1, full)
+    // and scheduled across its boundaries
+#pragma unroll
     for (int it = 0; it < P; ++it) {
         const bool first = it == 0;            // first iterate is time-independent
         const int nfe = first ? 1 : NE - 1;    // projected flux time modes this iteration
